@@ -1,0 +1,179 @@
+/*
+ * liblz — device-resident decoder for the absolute-offset block LZ77 codec
+ * (arXiv 2606.18900), on one AMD Instinct MI355X (gfx950).
+ *
+ * The method (paper, Background section): every LZ77 back-reference is an
+ * absolute position in the decompressed output; the output is cut into
+ * fixed-size blocks (Block Granularity section: 16 KB); each block stores four
+ * streams (literals, match lengths, absolute offsets, command sequence); a
+ * block can be decoded once the blocks holding its source bytes are done.
+ * This library decodes entirely on the GPU (Full Device-Resident Pipeline
+ * section): entropy decode and match resolution, ordered by dependency level
+ * ("wavefronts"), plus block-range decode and read-level random access through
+ * a read -> record-start index (Position-Invariant Random Access section and
+ * its Read-Level Index subsection), and range decode into a capped output
+ * window (Scale section).
+ *
+ * Conventions
+ *  - Every function returns an int status: LZ_OK (0) or a negative LZ_E* code;
+ *    lz_last_error() gives the text of the last failure of the calling thread.
+ *  - The caller owns every device buffer (archive, workspace, outputs,
+ *    scratch); the library never allocates device memory.  A handle keeps
+ *    non-owning pointers to the archive and workspace, which must outlive it.
+ *  - Device calls are asynchronous on the caller's HIP stream `s` (may be 0).
+ *    Arguments are checked on the host before anything is enqueued; errors
+ *    found by a kernel (corrupt payload, scratch exhausted, watchdog) are
+ *    latched in the workspace status word and returned by lz_sync_status().
+ *  - Offsets and sizes are bytes, 64-bit (Scale section: 64-bit fields).
+ *  - Calls on one handle must not overlap in time (one stream, or ordered
+ *    streams); different handles are independent.
+ */
+#ifndef LZ_H
+#define LZ_H
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LZ_OK        0
+#define LZ_EINVAL   (-1)  /* bad argument, null pointer, misaligned buffer   */
+#define LZ_EFORMAT  (-2)  /* bad magic/version/checksum or broken invariant   */
+#define LZ_ECAPACITY (-3) /* output/workspace/scratch too small; see *needed  */
+#define LZ_ERANGE   (-4)  /* offset+len > N, or read id outside [0, n_reads)  */
+#define LZ_ENOINDEX (-5)  /* archive has no read index (not FASTQ)            */
+#define LZ_EDEVICE  (-6)  /* HIP runtime error; text in lz_last_error()       */
+#define LZ_ECORRUPT (-7)  /* device-side decode check failed                  */
+#define LZ_EBUDGET  (-8)  /* serving admission refused (budget)               */
+
+/* Encoder parameters (container format v1).  The match search is global and
+ * greedy with absolute source positions (Background section); blocks are
+ * 2^block_log2 bytes (16 KB in the paper); levels are capped at max_level-1. */
+typedef struct lz_params {
+  uint32_t block_log2;    /* 6..15; the device decoder takes 6..14           */
+  uint32_t max_level;     /* D, 1..64                                        */
+  uint32_t min_match;     /* m, hash_len..255                                */
+  uint32_t hash_len;      /* 4..16                                           */
+  uint32_t hash_bits;     /* 8..30                                           */
+  uint32_t chain_depth;   /* 0 = unbounded                                   */
+  uint32_t window_log2;   /* 0 = unbounded                                   */
+  uint32_t lit_lanes;     /* max rANS lanes, literal stream, 1..256          */
+  uint32_t seq_lanes;     /* max rANS lanes, CMD/MLEN/OFF, 1..64             */
+  uint32_t prob_bits[4];  /* LIT, CMD, MLEN, OFF; 8..12 (device: LIT <= 12,
+                             the other three <= 10)                          */
+  uint32_t kind;          /* 0 raw, 1 FASTQ (writes the read index), 2 FASTA */
+  uint32_t level_penalty; /* beta: match score = length - beta * level       */
+  uint32_t threads;       /* encoder host threads (0 = all); no effect on bytes */
+} lz_params;
+
+typedef struct lz_info {
+  uint64_t n;               /* decompressed bytes N                          */
+  uint64_t n_blocks;        /* ceil(N / B)                                   */
+  uint64_t n_reads;         /* FASTQ records (0 without a read index)        */
+  uint64_t archive_len;     /* total archive bytes                           */
+  uint64_t source_fnv;      /* FNV-1a-64 over the LE64 block hashes          */
+  uint64_t workspace_bytes; /* device workspace lz_open needs                */
+  uint32_t block_log2, max_level, n_levels, offset_width, max_record_len, kind;
+} lz_info;
+
+/* One request of a batch: kind 0 = read lookup (a = read id), kind 1 = byte
+ * range (a = offset, b = length).  Results are concatenated in request order. */
+typedef struct lz_request {
+  int64_t kind, a, b;
+} lz_request;
+
+/* Launch knobs (chosen by the autotuner; none of them changes a decoded byte). */
+typedef struct lz_tuning {
+  uint32_t sync_mode;   /* 0 = per-level launches, 1 = one persistent launch
+                           with per-block completion flags                   */
+  uint32_t wg_per_cu;   /* persistent grid = wg_per_cu * CUs (1..4)          */
+  uint32_t spin_limit;  /* watchdog: max polls of a dependency flag before the
+                           kernel gives up with LZ_ECORRUPT (0 = default)     */
+} lz_tuning;
+
+typedef struct lz_handle lz_handle;
+
+/* ---- host ------------------------------------------------------------- */
+
+/* Fill *p with the default profile: 16 KB blocks, D = 64, m = h = 16,
+ * hash_bits 20, chain 64, no window, 256/64 lanes, P = 12/10/10/10,
+ * level_penalty 32. */
+int lz_params_default(lz_params* p);
+
+/* Compress src[0..n) (host memory).  On success *archive (host memory owned by
+ * the library, free with lz_free) holds *archive_len bytes.  Errors: EINVAL
+ * (bad parameters, or kind FASTQ and the input is not whole 4-line records). */
+int lz_encode(const uint8_t* src, uint64_t n, const lz_params* p,
+              uint8_t** archive, uint64_t* archive_len);
+void lz_free(void* p);
+
+/* Parse the 128-byte header of a host copy of an archive (len >= 128) and
+ * report sizes, including the workspace lz_open needs.  EFORMAT on a bad header. */
+int lz_info_get(const uint8_t* host_archive, uint64_t len, lz_info* out);
+
+/* ---- device ----------------------------------------------------------- */
+
+/* Bind an archive already in device memory.  Copies header, directory and
+ * dependency lists to the host once and validates every container invariant
+ * (EFORMAT), checks device limits (EFORMAT: block_log2 > 14, LIT P > 12 or
+ * CMD/MLEN/OFF P > 10), then builds the level-ordered block queue and the rANS
+ * lookup tables in the workspace (d_ws, ws_len bytes, 256-byte aligned;
+ * ECAPACITY if smaller than lz_info.workspace_bytes).  Synchronises s. */
+int lz_open(const uint8_t* d_archive, uint64_t len, void* d_ws, uint64_t ws_len,
+            hipStream_t s, lz_handle** h);
+int lz_close(lz_handle* h);
+int lz_get_info(const lz_handle* h, lz_info* out);
+int lz_set_tuning(lz_handle* h, const lz_tuning* t);
+int lz_get_tuning(const lz_handle* h, lz_tuning* t);
+
+/* Whole-file decode (Mode 2 of the Full Device-Resident Pipeline section):
+ * d_out[0..N) = x.  d_out must be 16-byte aligned, cap >= N (else ECAPACITY). */
+int lz_decode_all(lz_handle* h, uint8_t* d_out, uint64_t cap, hipStream_t s);
+
+/* Range decode (Position-Invariant Random Access section): d_out[0..len) =
+ * x[offset, offset+len).  Decodes the covering blocks plus their dependency
+ * closure; blocks that cannot go straight into d_out are decoded into
+ * d_scratch (16-byte aligned, scratch_len bytes; one block-sized slot per such
+ * block).  len = 0 is a no-op.  ERANGE if offset + len > N.  A scratch shortage
+ * found on the device is reported by lz_sync_status as ECAPACITY. */
+int lz_decode_range(lz_handle* h, uint64_t offset, uint64_t len, uint8_t* d_out,
+                    void* d_scratch, uint64_t scratch_len, hipStream_t s);
+
+/* Read lookup (Read-Level Index subsection): for d_ids[0..n) (device, int64)
+ * write the 4-line records, concatenated in request order, to d_out and their
+ * exclusive prefix offsets to d_offsets[0..n] (device, u64).  cap must be >=
+ * n * max_record_len (ECAPACITY otherwise).  ENOINDEX without a read index;
+ * an id outside [0, n_reads) is latched as ERANGE on the device. */
+int lz_read_lookup(lz_handle* h, const int64_t* d_ids, uint64_t n, uint8_t* d_out,
+                   uint64_t cap, uint64_t* d_offsets, void* d_scratch,
+                   uint64_t scratch_len, hipStream_t s);
+
+/* Batched requests (mixed reads and ranges) resolved together: one closure
+ * over all requests, one decode launch over the shared level-ordered queue,
+ * then a gather into d_out at d_offsets (device, n+1 entries).  d_reqs is a
+ * device array of n lz_request.  n_max sizes the device-side request
+ * capacity the call was planned for (n <= n_max); the sequence of launches
+ * depends only on (handle, n_max), so it can be captured once in a HIP graph
+ * and replayed with new request contents.  cap bounds the output; a larger
+ * total is latched as ECAPACITY. */
+int lz_decode_batch(lz_handle* h, const lz_request* d_reqs, const uint32_t* d_n,
+                    uint64_t n_max, uint8_t* d_out, uint64_t cap, uint64_t* d_offsets,
+                    void* d_scratch, uint64_t scratch_len, hipStream_t s);
+
+/* Per-block FNV-1a-64 of d_out[0..N) compared on the device with the
+ * directory's source hashes (Experimental Setup: FNV on device paths);
+ * mismatches are latched as ECORRUPT.  *d_tree (device u64) receives the
+ * tree hash.  d_scratch needs 8 * n_blocks bytes. */
+int lz_verify(lz_handle* h, const uint8_t* d_out, uint64_t* d_tree,
+              void* d_scratch, uint64_t scratch_len, hipStream_t s);
+
+/* Synchronise s, return and clear the latched device status (LZ_OK if none). */
+int lz_sync_status(lz_handle* h, hipStream_t s);
+
+const char* lz_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

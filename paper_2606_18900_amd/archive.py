@@ -1,0 +1,166 @@
+"""Python face of liblz: host encode, and an Archive bound on the GPU whose
+decode calls enqueue HIP kernels on the current torch stream.  torch provides
+device memory and streams only; every decode step runs in liblz's kernels."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+
+def encode(data, **params) -> bytes:
+    """Compress host bytes (lz_encode).  Keyword arguments override the
+    default lz_params fields (kind, min_match, level_penalty, ...)."""
+    if isinstance(data, np.ndarray):
+        a = np.ascontiguousarray(data, dtype=np.uint8)
+    else:
+        a = np.frombuffer(memoryview(data), dtype=np.uint8)
+    p = _lib.default_params(**params)
+    out = C.c_void_p()
+    n = C.c_uint64()
+    check(lib().lz_encode(C.c_void_p(a.ctypes.data if a.size else 0), a.size, C.byref(p),
+                          C.byref(out), C.byref(n)))
+    try:
+        return C.string_at(out.value, n.value)
+    finally:
+        lib().lz_free(out)
+
+
+def info(archive: bytes) -> _lib.Info:
+    i = _lib.Info()
+    a = np.frombuffer(memoryview(archive), dtype=np.uint8)
+    check(lib().lz_info_get(C.c_void_p(a.ctypes.data), a.size, C.byref(i)))
+    return i
+
+
+def _ptr(t: torch.Tensor | None) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr() if t is not None and t.numel() else 0)
+
+
+def _stream(stream=None) -> C.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Archive:
+    """An archive resident in HBM plus its decoder workspace (lz_open)."""
+
+    def __init__(self, archive, device: str | torch.device = "cuda:0", stream=None):
+        self.device = torch.device(device)
+        if isinstance(archive, torch.Tensor):
+            assert archive.dtype == torch.uint8 and archive.is_cuda and archive.is_contiguous()
+            self.d_archive = archive
+            head = archive[:128].cpu().numpy().tobytes()
+        else:
+            host = torch.frombuffer(bytearray(archive), dtype=torch.uint8)
+            self.d_archive = torch.empty(host.numel(), dtype=torch.uint8, device=self.device)
+            self.d_archive.copy_(host)
+            head = bytes(archive[:128])
+        i = _lib.Info()
+        check(lib().lz_info_get(head, len(head) if len(head) < 128 else self.d_archive.numel(), C.byref(i)))
+        self.info = i
+        self.ws = torch.empty(max(i.workspace_bytes, 256), dtype=torch.uint8, device=self.device)
+        self.h = C.c_void_p()
+        check(lib().lz_open(_ptr(self.d_archive), self.d_archive.numel(), _ptr(self.ws),
+                            self.ws.numel(), _stream(stream), C.byref(self.h)))
+
+    # -- properties
+    @property
+    def n(self) -> int:
+        return int(self.info.n)
+
+    @property
+    def n_blocks(self) -> int:
+        return int(self.info.n_blocks)
+
+    @property
+    def n_reads(self) -> int:
+        return int(self.info.n_reads)
+
+    def close(self):
+        if self.h:
+            lib().lz_close(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- tuning
+    def tuning(self) -> _lib.Tuning:
+        t = _lib.Tuning()
+        check(lib().lz_get_tuning(self.h, C.byref(t)))
+        return t
+
+    def set_tuning(self, sync_mode: int | None = None, wg_per_cu: int | None = None,
+                   spin_limit: int | None = None):
+        t = self.tuning()
+        if sync_mode is not None:
+            t.sync_mode = sync_mode
+        if wg_per_cu is not None:
+            t.wg_per_cu = wg_per_cu
+        if spin_limit is not None:
+            t.spin_limit = spin_limit
+        check(lib().lz_set_tuning(self.h, C.byref(t)))
+
+    # -- decode
+    def decode_all(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(max(self.n, 1), dtype=torch.uint8, device=self.device)
+        check(lib().lz_decode_all(self.h, _ptr(out), out.numel(), _stream(stream)))
+        return out[: self.n]
+
+    def decode_range(self, offset: int, length: int, out: torch.Tensor | None = None,
+                     scratch: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(max(length, 1), dtype=torch.uint8, device=self.device)
+        if scratch is None:
+            scratch = self.default_scratch(1, length)
+        check(lib().lz_decode_range(self.h, offset, length, _ptr(out), _ptr(scratch),
+                                    scratch.numel(), _stream(stream)))
+        return out[:length]
+
+    def read_lookup(self, ids, out: torch.Tensor | None = None,
+                    offsets: torch.Tensor | None = None, scratch: torch.Tensor | None = None,
+                    stream=None):
+        ids = torch.as_tensor(ids, dtype=torch.int64, device=self.device).contiguous()
+        n = ids.numel()
+        cap = max(1, n * int(self.info.max_record_len))
+        if out is None:
+            out = torch.empty(cap, dtype=torch.uint8, device=self.device)
+        if offsets is None:
+            offsets = torch.empty(n + 1, dtype=torch.int64, device=self.device)
+        if scratch is None:
+            scratch = self.default_scratch(n, cap)
+        check(lib().lz_read_lookup(self.h, _ptr(ids), n, _ptr(out), out.numel(), _ptr(offsets),
+                                   _ptr(scratch), scratch.numel(), _stream(stream)))
+        return out, offsets
+
+    def decode_batch(self, reqs: torch.Tensor, n: torch.Tensor, n_max: int, out: torch.Tensor,
+                     offsets: torch.Tensor, scratch: torch.Tensor, stream=None):
+        """reqs: device int64 [n_max, 3] (kind, a, b); n: device uint32/int32 [1]."""
+        check(lib().lz_decode_batch(self.h, _ptr(reqs), _ptr(n), n_max, _ptr(out), out.numel(),
+                                    _ptr(offsets), _ptr(scratch), scratch.numel(), _stream(stream)))
+
+    def verify(self, out: torch.Tensor, stream=None) -> torch.Tensor:
+        tree = torch.zeros(1, dtype=torch.int64, device=self.device)
+        scratch = torch.empty(max(8 * self.n_blocks, 8), dtype=torch.uint8, device=self.device)
+        check(lib().lz_verify(self.h, _ptr(out), _ptr(tree), _ptr(scratch), scratch.numel(),
+                              _stream(stream)))
+        return tree
+
+    def sync_status(self, stream=None) -> None:
+        check(lib().lz_sync_status(self.h, _stream(stream)))
+
+    def default_scratch(self, n_requests: int, out_bytes: int) -> torch.Tensor:
+        """Scratch sized for request spans plus one slot per block of the file
+        (an upper bound on any closure)."""
+        B = 1 << int(self.info.block_log2)
+        nbytes = 64 * (n_requests + 1) + B * self.n_blocks + 4096
+        return torch.empty(nbytes, dtype=torch.uint8, device=self.device)

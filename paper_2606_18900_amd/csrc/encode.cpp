@@ -1,0 +1,536 @@
+// Host encoder (lz_encode) for container format v1.
+//
+// Global greedy match search whose matches carry absolute source positions in
+// the decompressed output (paper, Background section), fixed-size blocks
+// (Block Granularity section), four streams per block coded with interleaved
+// rANS, dependency levels capped at max_level - 1, a read index for FASTQ
+// (Read-Level Index subsection) and 64-bit positions (Scale section).
+//
+// Match policy at position p of block b (blocks [bB, min(bB+B, N))):
+//   candidates: the hash chain of the first h bytes at p (most recent first,
+//   at most C, none older than 2^R), then the first position ever seen with
+//   that hash; length = common prefix of x[q:] and x[p:] capped at the block
+//   end; level lv = 0 for a source inside the block, else 1 + the highest level
+//   among the earlier blocks the source touches; score = length - beta * lv;
+//   drop lv > D - 1 or score < m; best score wins, then lower lv, then the
+//   first candidate seen.  A match advances p by its length, otherwise p += 1.
+// The parse is sequential (levels feed back into later choices); the per-block
+// stream coding, hashing and table counting run on host threads.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "lz.h"
+#include "lz_internal.h"
+
+namespace {
+
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+
+inline uint64_t load_le(const uint8_t* p, uint32_t n) {
+  uint64_t v = 0;
+  std::memcpy(&v, p, n);  // little-endian host
+  return v;
+}
+
+struct Hasher {
+  uint32_t h, H;
+  uint64_t mask0, mask1;
+  Hasher(uint32_t h_, uint32_t H_) : h(h_), H(H_) {
+    uint32_t n0 = h < 8 ? h : 8, n1 = h > 8 ? h - 8 : 0;
+    mask0 = n0 == 8 ? ~0ull : ((1ull << (8 * n0)) - 1);
+    mask1 = n1 == 8 ? ~0ull : ((1ull << (8 * n1)) - 1);
+  }
+  // requires p + h <= n; reads exactly h bytes unless 16 are available
+  inline uint64_t operator()(const uint8_t* x, uint64_t p, uint64_t n) const {
+    uint64_t v0, v1;
+    if (p + 16 <= n) {
+      std::memcpy(&v0, x + p, 8);
+      std::memcpy(&v1, x + p + 8, 8);
+      v0 &= mask0;
+      v1 &= mask1;
+    } else {
+      v0 = load_le(x + p, h < 8 ? h : 8);
+      v1 = h > 8 ? load_le(x + p + 8, h - 8) : 0;
+    }
+    uint64_t t = v0 * kGolden;
+    t = (t << 29) | (t >> 35);
+    return ((t ^ v1) * kGolden) >> (64 - H);
+  }
+};
+
+inline uint64_t lcp(const uint8_t* x, uint64_t q, uint64_t p, uint64_t cap) {
+  uint64_t L = 0;
+  while (L + 8 <= cap) {
+    uint64_t a, b;
+    std::memcpy(&a, x + q + L, 8);
+    std::memcpy(&b, x + p + L, 8);
+    uint64_t d = a ^ b;
+    if (d) return L + (__builtin_ctzll(d) >> 3);
+    L += 8;
+  }
+  while (L < cap && x[q + L] == x[p + L]) L++;
+  return L;
+}
+
+struct Parse {
+  std::vector<uint32_t> ll, ml;
+  std::vector<uint64_t> of;
+  std::vector<uint64_t> seq_ptr;   // n_blocks + 1
+  std::vector<uint16_t> level;
+  std::vector<uint64_t> dep_ptr;   // n_blocks + 1
+  std::vector<uint32_t> dep_idx;
+};
+
+template <typename Pos>
+int parse_impl(const uint8_t* x, uint64_t n, const lz_params& pr, Parse& out) {
+  const uint32_t bl = pr.block_log2;
+  const uint64_t B = 1ull << bl, nb = (n + B - 1) >> bl;
+  const uint32_t h = pr.hash_len, m = pr.min_match, D = pr.max_level;
+  const uint64_t C = pr.chain_depth ? pr.chain_depth : ~0ull;
+  const uint64_t win = pr.window_log2 ? (1ull << pr.window_log2) : ~0ull;
+  const int64_t beta = pr.level_penalty;
+  const Pos kNone = (Pos)~(Pos)0;
+  Hasher hash(h, pr.hash_bits);
+  std::vector<Pos> head(1ull << pr.hash_bits, kNone), anchor(1ull << pr.hash_bits, kNone);
+  // prev link of position q lives at q & ring_mask (a full array without a window)
+  uint64_t ring = n;
+  if (pr.window_log2 && (1ull << pr.window_log2) < n) ring = 1ull << pr.window_log2;
+  const uint64_t ring_mask = (ring == n) ? ~0ull : ring - 1;
+  std::vector<Pos> prev(ring ? ring : 1, kNone);
+
+  out.seq_ptr.assign(nb + 1, 0);
+  out.level.assign(nb, 0);
+  out.dep_ptr.assign(nb + 1, 0);
+  std::vector<uint8_t> mark(nb, 0);
+  std::vector<uint32_t> touched;
+  uint64_t ins = 0;
+  for (uint64_t b = 0; b < nb; b++) {
+    const uint64_t sb = b << bl, eb = std::min(sb + B, n);
+    uint64_t p = sb, lit = sb;
+    uint32_t blevel = 0;
+    while (p < eb) {
+      for (; ins < p; ins++) {
+        if (ins + h > n) continue;
+        uint64_t hv = hash(x, ins, n);
+        prev[ins & ring_mask] = head[hv];
+        head[hv] = (Pos)ins;
+        if (anchor[hv] == kNone) anchor[hv] = (Pos)ins;
+      }
+      uint64_t bestL = 0, bestQ = 0;
+      uint32_t bestLv = 0;
+      int64_t bestSc = 0;
+      if (p + m <= eb) {
+        const uint64_t hv = hash(x, p, n);
+        const Pos a = anchor[hv];
+        bool anchor_seen = false;
+        auto consider = [&](uint64_t q) {
+          uint64_t L = lcp(x, q, p, eb - p);
+          if (L < m) return;
+          uint32_t lv = 0;
+          if (q < sb) {
+            uint64_t hi = std::min(q + L, sb);
+            uint32_t mx = 0;
+            for (uint64_t k = q >> bl; k <= (hi - 1) >> bl; k++) mx = std::max<uint32_t>(mx, out.level[k]);
+            lv = mx + 1;
+          }
+          if (lv > D - 1) return;
+          int64_t sc = (int64_t)L - beta * (int64_t)lv;
+          if (sc < (int64_t)m) return;
+          if (bestL == 0 || sc > bestSc || (sc == bestSc && lv < bestLv)) {
+            bestSc = sc;
+            bestL = L;
+            bestQ = q;
+            bestLv = lv;
+          }
+        };
+        Pos q = head[hv];
+        uint64_t cnt = 0;
+        while (q != kNone && cnt < C && p - (uint64_t)q <= win) {
+          if (q == a) anchor_seen = true;
+          consider(q);
+          q = prev[(uint64_t)q & ring_mask];
+          cnt++;
+        }
+        if (a != kNone && !anchor_seen) consider(a);
+      }
+      if (bestL) {
+        out.ll.push_back((uint32_t)(p - lit));
+        out.ml.push_back((uint32_t)bestL);
+        out.of.push_back(bestQ);
+        if (bestQ < sb) {
+          uint64_t hi = std::min(bestQ + bestL, sb);
+          for (uint64_t k = bestQ >> bl; k <= (hi - 1) >> bl; k++)
+            if (!mark[k]) { mark[k] = 1; touched.push_back((uint32_t)k); }
+        }
+        blevel = std::max(blevel, bestLv);
+        p += bestL;
+        lit = p;
+      } else {
+        p++;
+      }
+    }
+    if (lit < eb) {
+      out.ll.push_back((uint32_t)(eb - lit));
+      out.ml.push_back(0);
+      out.of.push_back(0);
+    }
+    out.seq_ptr[b + 1] = out.ll.size();
+    out.level[b] = (uint16_t)blevel;
+    std::sort(touched.begin(), touched.end());
+    for (uint32_t k : touched) { mark[k] = 0; out.dep_idx.push_back(k); }
+    touched.clear();
+    out.dep_ptr[b + 1] = out.dep_idx.size();
+  }
+  return LZ_OK;
+}
+
+// ---------------------------------------------------------------- rANS
+// Normalise counts to sum 2^P (floor(c*M/T), at least 1 per seen symbol;
+// remainder to the most frequent symbol, lowest value on ties; an excess is
+// removed one unit at a time from the largest f > 1, lowest value on ties).
+int normalize(const uint64_t* counts, uint32_t P, uint16_t* freq) {
+  uint64_t T = 0;
+  for (int s = 0; s < 256; s++) T += counts[s];
+  std::memset(freq, 0, 512);
+  if (!T) return LZ_OK;
+  const uint64_t M = 1ull << P;
+  int64_t sum = 0;
+  for (int s = 0; s < 256; s++)
+    if (counts[s]) {
+      uint64_t f = std::max<uint64_t>(1, counts[s] * M / T);
+      freq[s] = (uint16_t)f;
+      sum += (int64_t)f;
+    }
+  int64_t d = (int64_t)M - sum;
+  if (d > 0) {
+    int best = -1;
+    for (int s = 0; s < 256; s++)
+      if (counts[s] && (best < 0 || counts[s] > counts[best])) best = s;
+    freq[best] = (uint16_t)(freq[best] + d);
+  }
+  while (d < 0) {
+    int best = -1;
+    for (int s = 0; s < 256; s++)
+      if (freq[s] > 1 && (best < 0 || freq[s] > freq[best])) best = s;
+    if (best < 0) return LZ_EINVAL;
+    freq[best]--;
+    d++;
+  }
+  return LZ_OK;
+}
+
+uint32_t lanes_for(uint32_t n, uint32_t max_lanes) {
+  uint32_t q = n >> 4, k = 1;
+  while (k * 2 <= q) k *= 2;
+  return std::min(k, max_lanes);
+}
+
+struct Table {
+  uint16_t f[256];
+  uint32_t c[257];
+  uint32_t P;
+};
+
+// Encode sym[0..n) with K interleaved lanes (symbol i -> lane i mod K), from
+// the last symbol to the first; emits the record body into `body`.
+void rans_body(const uint8_t* sym, uint32_t n, const Table& t, uint32_t K,
+               std::vector<uint8_t>& body, uint32_t& n_words) {
+  const uint32_t G = (K + 63) / 64;
+  uint32_t x[256];
+  for (uint32_t k = 0; k < K; k++) x[k] = 1u << 16;
+  std::vector<uint16_t> w(n);
+  std::vector<uint8_t> has(n, 0);
+  for (uint32_t i = n; i-- > 0;) {
+    uint32_t k = i % K, s = sym[i], f = t.f[s];
+    uint64_t xm = (uint64_t)f << (32 - t.P);
+    uint64_t v = x[k];
+    if (v >= xm) {
+      w[i] = (uint16_t)(v & 0xFFFF);
+      has[i] = 1;
+      v >>= 16;
+    }
+    x[k] = (uint32_t)((v / f) * (1ull << t.P) + (v % f) + t.c[s]);
+  }
+  uint32_t gw[4] = {0, 0, 0, 0}, nw = 0;
+  for (uint32_t i = 0; i < n; i++)
+    if (has[i]) { gw[(i % K) >> 6]++; nw++; }
+  body.resize(4ull * K + 4ull * G + 2ull * nw);
+  uint8_t* o = body.data();
+  for (uint32_t k = 0; k < K; k++, o += 4) std::memcpy(o, &x[k], 4);
+  for (uint32_t g = 0; g < G; g++, o += 4) std::memcpy(o, &gw[g], 4);
+  // words of group g in ascending symbol index: lanes 64g..64g+63 of each round
+  for (uint32_t g = 0; g < G; g++) {
+    uint32_t k0 = 64 * g, k1 = std::min(K, k0 + 64);
+    for (uint32_t r = 0; (uint64_t)r * K < n; r++)
+      for (uint32_t k = k0; k < k1; k++) {
+        uint64_t i = (uint64_t)r * K + k;
+        if (i >= n) break;
+        if (has[i]) { std::memcpy(o, &w[i], 2); o += 2; }
+      }
+  }
+  n_words = nw;
+}
+
+void put_stream(std::vector<uint8_t>& outb, const uint8_t* sym, uint32_t n, const Table& t,
+                uint32_t max_lanes) {
+  uint8_t hdr[16] = {0};
+  std::memcpy(hdr + 4, &n, 4);
+  auto pad = [&]() { while (outb.size() & 15) outb.push_back(0); };
+  if (n == 0) {
+    hdr[0] = kModeEmpty;
+    outb.insert(outb.end(), hdr, hdr + 16);
+    return;
+  }
+  bool same = true;
+  for (uint32_t i = 1; i < n && same; i++) same = sym[i] == sym[0];
+  if (same) {
+    hdr[0] = kModeConst;
+    hdr[1] = sym[0];
+    outb.insert(outb.end(), hdr, hdr + 16);
+    return;
+  }
+  uint32_t K = lanes_for(n, max_lanes), nw = 0;
+  std::vector<uint8_t> body;
+  rans_body(sym, n, t, K, body, nw);
+  if (body.size() >= n) {
+    hdr[0] = kModeRaw;
+    std::memcpy(hdr + 12, &n, 4);
+    outb.insert(outb.end(), hdr, hdr + 16);
+    outb.insert(outb.end(), sym, sym + n);
+  } else {
+    hdr[0] = kModeRans;
+    uint16_t k16 = (uint16_t)K;
+    uint32_t bl = (uint32_t)body.size();
+    std::memcpy(hdr + 2, &k16, 2);
+    std::memcpy(hdr + 8, &nw, 4);
+    std::memcpy(hdr + 12, &bl, 4);
+    outb.insert(outb.end(), hdr, hdr + 16);
+    outb.insert(outb.end(), body.begin(), body.end());
+  }
+  pad();
+}
+
+uint64_t fnv1a(const uint8_t* p, uint64_t n, uint64_t h) {
+  for (uint64_t i = 0; i < n; i++) h = (h ^ p[i]) * kFnvPrime;
+  return h;
+}
+
+template <typename F>
+void parallel_for(uint64_t n, unsigned threads, F&& f) {
+  if (threads <= 1 || n < 2) {
+    for (uint64_t i = 0; i < n; i++) f(i, 0u);
+    return;
+  }
+  std::atomic<uint64_t> next{0};
+  std::vector<std::thread> ts;
+  for (unsigned t = 0; t < threads; t++)
+    ts.emplace_back([&, t]() {
+      for (;;) {
+        uint64_t i = next.fetch_add(1);
+        if (i >= n) break;
+        f(i, t);
+      }
+    });
+  for (auto& t : ts) t.join();
+}
+
+int check(const lz_params& p) {
+  if (p.block_log2 < 6 || p.block_log2 > 15) return LZ_EINVAL;
+  if (p.max_level < 1 || p.max_level > 64) return LZ_EINVAL;
+  if (p.hash_len < 4 || p.hash_len > 16) return LZ_EINVAL;
+  if (p.min_match < p.hash_len || p.min_match > 255) return LZ_EINVAL;
+  if (p.hash_bits < 8 || p.hash_bits > 30) return LZ_EINVAL;
+  if (p.window_log2 > 40 || p.chain_depth > 65535) return LZ_EINVAL;
+  if (p.lit_lanes < 1 || p.lit_lanes > 256 || p.seq_lanes < 1 || p.seq_lanes > 64) return LZ_EINVAL;
+  for (int k = 0; k < 4; k++)
+    if (p.prob_bits[k] < 8 || p.prob_bits[k] > 12) return LZ_EINVAL;
+  if (p.kind > 2 || p.level_penalty > 255) return LZ_EINVAL;
+  return LZ_OK;
+}
+
+}  // namespace
+
+extern "C" int lz_params_default(lz_params* p) {
+  if (!p) return lz_fail(LZ_EINVAL, "lz_params_default: null");
+  p->block_log2 = 14;
+  p->max_level = 64;
+  p->min_match = 16;
+  p->hash_len = 16;
+  p->hash_bits = 20;
+  p->chain_depth = 64;
+  p->window_log2 = 0;
+  p->lit_lanes = 256;
+  p->seq_lanes = 64;
+  p->prob_bits[0] = 12;
+  p->prob_bits[1] = p->prob_bits[2] = p->prob_bits[3] = 10;
+  p->kind = 0;
+  p->level_penalty = 32;
+  p->threads = 0;
+  return LZ_OK;
+}
+
+extern "C" void lz_free(void* p) { std::free(p); }
+
+extern "C" int lz_encode(const uint8_t* x, uint64_t n, const lz_params* pp, uint8_t** archive,
+                         uint64_t* archive_len) {
+  if (!pp || !archive || !archive_len || (n && !x)) return lz_fail(LZ_EINVAL, "lz_encode: null argument");
+  const lz_params pr = *pp;
+  if (check(pr)) return lz_fail(LZ_EINVAL, "lz_encode: parameter out of range");
+  unsigned threads = pr.threads ? pr.threads : std::max(1u, std::thread::hardware_concurrency());
+  const uint32_t bl = pr.block_log2;
+  const uint64_t B = 1ull << bl, nb = (n + B - 1) >> bl;
+  uint32_t w = 1;
+  {
+    uint64_t v = n ? n - 1 : 0;
+    uint32_t bits = 0;
+    while (v) { bits++; v >>= 1; }
+    w = std::max(1u, (bits + 7) / 8);
+  }
+  // read index: start of line 4r, counted by newlines
+  std::vector<uint64_t> ridx;
+  uint32_t max_rec = 0;
+  if (pr.kind == 1) {
+    if (n && x[n - 1] != '\n') return lz_fail(LZ_EINVAL, "lz_encode: FASTQ input does not end in a newline");
+    ridx.push_back(0);
+    uint64_t line = 0;
+    for (const uint8_t* q = x; (q = (const uint8_t*)std::memchr(q, '\n', (size_t)(x + n - q)));) {
+      q++;
+      if (++line % 4 == 0) ridx.push_back((uint64_t)(q - x));
+      if (q >= x + n) break;
+    }
+    if (line % 4) return lz_fail(LZ_EINVAL, "lz_encode: FASTQ input is not whole 4-line records");
+    for (size_t r = 0; r + 1 < ridx.size(); r++) {
+      uint64_t len = ridx[r + 1] - ridx[r];
+      if (len > 0xFFFFFFFFull) return lz_fail(LZ_EINVAL, "lz_encode: record too long");
+      max_rec = std::max<uint32_t>(max_rec, (uint32_t)len);
+    }
+  }
+  Parse ps;
+  int rc = n < (1ull << 32) - 1 ? parse_impl<uint32_t>(x, n, pr, ps) : parse_impl<uint64_t>(x, n, pr, ps);
+  if (rc) return lz_fail(rc, "lz_encode: parse failed");
+
+  // per-block stream bytes, built on demand
+  auto build = [&](uint64_t b, std::vector<uint8_t> s[4]) {
+    const uint64_t s0 = ps.seq_ptr[b], ns = ps.seq_ptr[b + 1] - s0;
+    uint64_t pos = b << bl;
+    s[kLit].clear();
+    s[kCmd].assign(2 * ns, 0);
+    s[kMlen].assign(2 * ns, 0);
+    s[kOff].assign(w * ns, 0);
+    for (uint64_t j = 0; j < ns; j++) {
+      uint32_t L = ps.ll[s0 + j], M = ps.ml[s0 + j];
+      uint64_t O = ps.of[s0 + j];
+      s[kLit].insert(s[kLit].end(), x + pos, x + pos + L);
+      pos += (uint64_t)L + M;
+      s[kCmd][j] = (uint8_t)L;
+      s[kCmd][ns + j] = (uint8_t)(L >> 8);
+      s[kMlen][j] = (uint8_t)M;
+      s[kMlen][ns + j] = (uint8_t)(M >> 8);
+      for (uint32_t k = 0; k < w; k++) s[kOff][k * ns + j] = (uint8_t)(O >> (8 * k));
+    }
+  };
+  std::vector<std::vector<uint64_t>> cnt(threads, std::vector<uint64_t>(4 * 256, 0));
+  parallel_for(nb, threads, [&](uint64_t b, unsigned t) {
+    std::vector<uint8_t> s[4];
+    build(b, s);
+    for (int k = 0; k < 4; k++)
+      for (uint8_t v : s[k]) cnt[t][k * 256 + v]++;
+  });
+  Table tab[4];
+  for (int k = 0; k < 4; k++) {
+    uint64_t c[256] = {0};
+    for (unsigned t = 0; t < threads; t++)
+      for (int s = 0; s < 256; s++) c[s] += cnt[t][k * 256 + s];
+    tab[k].P = pr.prob_bits[k];
+    if (normalize(c, tab[k].P, tab[k].f)) return lz_fail(LZ_EINVAL, "lz_encode: cannot normalise table");
+    tab[k].c[0] = 0;
+    for (int s = 0; s < 256; s++) tab[k].c[s + 1] = tab[k].c[s] + tab[k].f[s];
+  }
+  // per-block payloads in parallel
+  std::vector<std::vector<uint8_t>> pay(nb);
+  std::vector<uint64_t> bh(nb);
+  std::vector<uint32_t> nlit(nb);
+  parallel_for(nb, threads, [&](uint64_t b, unsigned) {
+    std::vector<uint8_t> s[4];
+    build(b, s);
+    static const int order[4] = {kCmd, kMlen, kOff, kLit};
+    for (int k : order)
+      put_stream(pay[b], s[k].data(), (uint32_t)s[k].size(), tab[k], k == kLit ? pr.lit_lanes : pr.seq_lanes);
+    const uint64_t sb = b << bl, eb = std::min(sb + B, n);
+    bh[b] = fnv1a(x + sb, eb - sb, kFnvBasis);
+    nlit[b] = (uint32_t)s[kLit].size();
+  });
+  // layout
+  auto al16 = [](uint64_t v) { return (v + 15) & ~15ull; };
+  const uint64_t ndeps = ps.dep_idx.size();
+  const uint64_t off_tables = kHeaderSize;
+  const uint64_t off_dir = off_tables + kTablesLen;
+  const uint64_t off_dep_ptr = al16(off_dir + nb * kDirEntry);
+  const uint64_t off_dep_idx = off_dep_ptr + 8 * (nb + 1);
+  const uint64_t off_payload = al16(off_dep_idx + 4 * ndeps);
+  std::vector<uint64_t> poff(nb + 1, 0);
+  for (uint64_t b = 0; b < nb; b++) poff[b + 1] = poff[b] + pay[b].size();
+  const uint64_t off_ridx = pr.kind == 1 ? al16(off_payload + poff[nb]) : 0;
+  const uint64_t total = pr.kind == 1 ? off_ridx + 8 * ridx.size() : al16(off_payload + poff[nb]);
+  uint8_t* A = (uint8_t*)std::calloc(total ? total : 1, 1);
+  if (!A) return lz_fail(LZ_EINVAL, "lz_encode: out of host memory");
+  for (int k = 0; k < 4; k++) std::memcpy(A + off_tables + 512 * k, tab[k].f, 512);
+  uint32_t n_levels = 0;
+  for (uint64_t b = 0; b < nb; b++) {
+    uint8_t* e = A + off_dir + b * kDirEntry;
+    uint32_t ns = (uint32_t)(ps.seq_ptr[b + 1] - ps.seq_ptr[b]), pl = (uint32_t)pay[b].size();
+    std::memcpy(e + 0, &poff[b], 8);
+    std::memcpy(e + 8, &pl, 4);
+    std::memcpy(e + 12, &ns, 4);
+    std::memcpy(e + 16, &nlit[b], 4);
+    std::memcpy(e + 20, &ps.level[b], 2);
+    std::memcpy(e + 24, &bh[b], 8);
+    n_levels = std::max<uint32_t>(n_levels, ps.level[b] + 1u);
+  }
+  std::memcpy(A + off_dep_ptr, ps.dep_ptr.data(), 8 * (nb + 1));
+  if (ndeps) std::memcpy(A + off_dep_idx, ps.dep_idx.data(), 4 * ndeps);
+  parallel_for(nb, threads, [&](uint64_t b, unsigned) {
+    std::memcpy(A + off_payload + poff[b], pay[b].data(), pay[b].size());
+  });
+  if (pr.kind == 1) std::memcpy(A + off_ridx, ridx.data(), 8 * ridx.size());
+  uint64_t tree = kFnvBasis;
+  for (uint64_t b = 0; b < nb; b++) tree = fnv1a((const uint8_t*)&bh[b], 8, tree);
+  // header
+  uint8_t* h = A;
+  std::memcpy(h, "LZAB", 4);
+  uint16_t ver = 1, flags = (uint16_t)((pr.kind == 1 ? 1u : 0u) | (pr.level_penalty << 8));
+  std::memcpy(h + 4, &ver, 2);
+  std::memcpy(h + 6, &flags, 2);
+  h[8] = (uint8_t)bl;
+  h[9] = (uint8_t)pr.max_level;
+  h[10] = (uint8_t)w;
+  h[11] = (uint8_t)pr.min_match;
+  h[12] = (uint8_t)pr.hash_len;
+  h[13] = (uint8_t)pr.kind;
+  h[14] = (uint8_t)(pr.lit_lanes - 1);
+  h[15] = (uint8_t)pr.seq_lanes;
+  for (int k = 0; k < 4; k++) h[16 + k] = (uint8_t)pr.prob_bits[k];
+  h[20] = (uint8_t)pr.hash_bits;
+  h[21] = (uint8_t)pr.window_log2;
+  uint16_t cd = (uint16_t)pr.chain_depth;
+  std::memcpy(h + 22, &cd, 2);
+  uint64_t n_reads = ridx.empty() ? 0 : ridx.size() - 1;
+  uint64_t f64[] = {n, nb, n_reads};
+  std::memcpy(h + 24, f64, 24);
+  std::memcpy(h + 48, &max_rec, 4);
+  std::memcpy(h + 52, &n_levels, 4);
+  uint64_t offs[] = {off_tables, off_dir, off_dep_ptr, off_dep_idx, off_payload, off_ridx, total, tree};
+  std::memcpy(h + 56, offs, 64);
+  uint64_t hf = fnv1a(h, 120, kFnvBasis);
+  std::memcpy(h + 120, &hf, 8);
+  *archive = A;
+  *archive_len = total;
+  return LZ_OK;
+}

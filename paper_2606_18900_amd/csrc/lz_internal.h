@@ -1,0 +1,84 @@
+// Internal definitions shared by the library's host and device sources:
+// container format v1 layout constants, the handle, and error reporting.
+#pragma once
+#include <cstdint>
+
+#include "lz.h"
+
+constexpr uint64_t kHeaderSize = 128;
+constexpr uint64_t kTablesLen = 4 * 256 * 2;   // 4 tables of 256 u16 frequencies
+constexpr uint64_t kDirEntry = 32;             // payload_off u64, payload_len u32,
+                                               // n_seq u32, n_lit u32, level u16,
+                                               // reserved u16, block_fnv u64
+constexpr uint64_t kFnvBasis = 0xcbf29ce484222325ull;
+constexpr uint64_t kFnvPrime = 0x00000100000001b3ull;
+
+enum StreamKind { kLit = 0, kCmd = 1, kMlen = 2, kOff = 3 };
+enum StreamMode { kModeEmpty = 0, kModeConst = 1, kModeRaw = 2, kModeRans = 3 };
+
+// device limits of the decoder
+constexpr uint32_t kMaxBlockLog2 = 14;
+constexpr uint32_t kMaxPLit = 12;
+constexpr uint32_t kMaxPSeq = 10;
+constexpr uint32_t kMaxLevels = 64;
+
+// status bits latched by kernels in the workspace status word
+enum : uint32_t {
+  kStCorrupt = 1u,     // payload failed a decode check
+  kStCapacity = 2u,    // scratch slots or output capacity exhausted
+  kStRange = 4u,       // request outside the file / read id out of range
+  kStWatchdog = 8u,    // a dependency wait exceeded the spin limit
+  kStHash = 16u,       // FNV verification mismatch
+};
+
+int lz_fail(int code, const char* fmt, ...);
+
+// Everything a kernel needs to find an archive's sections in device memory.
+struct ArchiveView {
+  const uint8_t* base;     // device
+  uint64_t n, n_blocks, n_reads;
+  uint64_t off_tables, off_dir, off_dep_ptr, off_dep_idx, off_payload, off_ridx;
+  uint32_t block_log2, offset_width, min_match, lit_lanes, seq_lanes;
+  uint32_t prob_bits[4];
+  uint32_t n_levels, max_record_len, kind;
+};
+
+// Workspace carve-up (device pointers), see lz_open.
+struct Workspace {
+  uint32_t* lut;          // 4096 + 3*1024 packed decode entries
+  uint32_t* queue;        // n_blocks: whole-file level-ordered block ids
+  uint32_t* level_ptr;    // 65: level offsets into queue
+  uint32_t* flags;        // n_blocks: completion epoch per block
+  uint32_t* mark;         // n_blocks: request epoch per block (closure)
+  uint64_t* addr;         // n_blocks: device address of decoded block bytes
+  uint32_t* rqueue;       // n_blocks: request closure queue (level order)
+  uint32_t* rlevel_ptr;   // 65 + 65: level offsets / cursors of rqueue
+  uint32_t* frontier;     // 2 * n_blocks: closure work lists
+  uint32_t* ctl;          // control words (see kCtl*)
+  uint64_t* req_span;     // per request [start, end) bytes (2 * max_req)
+  uint64_t max_req;
+};
+
+// control words in Workspace::ctl
+enum : uint32_t {
+  kCtlStatus = 0,     // latched status bits
+  kCtlTicket = 1,     // persistent-kernel ticket counter
+  kCtlEpoch = 2,      // completion epoch (flags)
+  kCtlREpoch = 3,     // request epoch (marks)
+  kCtlClosure = 4,    // number of blocks in the request closure
+  kCtlSlots = 5,      // scratch slots used
+  kCtlFront0 = 6,     // frontier sizes
+  kCtlFront1 = 7,
+  kCtlTotalLo = 8,    // total output bytes of a request batch (u64)
+  kCtlTotalHi = 9,
+  kCtlWords = 16,
+};
+
+struct lz_handle {
+  ArchiveView av;
+  Workspace ws;
+  lz_tuning tune;
+  int n_cu;
+  uint32_t level_count[kMaxLevels];   // host copy of the whole-file level histogram
+  uint32_t epoch;                     // host mirror of the completion epoch
+};
