@@ -60,8 +60,7 @@ typedef struct lz_params {
   uint32_t window_log2;   /* 0 = unbounded                                   */
   uint32_t lit_lanes;     /* max rANS lanes, literal stream, 1..256          */
   uint32_t seq_lanes;     /* max rANS lanes, CMD/MLEN/OFF, 1..64             */
-  uint32_t prob_bits[4];  /* LIT, CMD, MLEN, OFF; 8..12 (device: LIT <= 12,
-                             the other three <= 10)                          */
+  uint32_t prob_bits[4];  /* LIT, CMD, MLEN, OFF; 8..12                      */
   uint32_t kind;          /* 0 raw, 1 FASTQ (writes the read index), 2 FASTA */
   uint32_t level_penalty; /* beta: match score = length - beta * level       */
   uint32_t threads;       /* encoder host threads (0 = all); no effect on bytes */
@@ -116,8 +115,8 @@ int lz_info_get(const uint8_t* host_archive, uint64_t len, lz_info* out);
 
 /* Bind an archive already in device memory.  Copies header, directory and
  * dependency lists to the host once and validates every container invariant
- * (EFORMAT), checks device limits (EFORMAT: block_log2 > 14, LIT P > 12 or
- * CMD/MLEN/OFF P > 10), then builds the level-ordered block queue and the rANS
+ * (EFORMAT), checks device limits (EFORMAT: block_log2 > 14, N >= 2^40, more
+ * than 1025 sequences per block possible), then builds the level-ordered block queue and the rANS
  * lookup tables in the workspace (d_ws, ws_len bytes, 256-byte aligned;
  * ECAPACITY if smaller than lz_info.workspace_bytes).  Synchronises s. */
 int lz_open(const uint8_t* d_archive, uint64_t len, void* d_ws, uint64_t ws_len,

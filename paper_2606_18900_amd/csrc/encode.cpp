@@ -88,8 +88,11 @@ struct Parse {
   std::vector<uint32_t> dep_idx;
 };
 
+template <typename F>
+void parallel_for(uint64_t n, unsigned threads, F&& f);
+
 template <typename Pos>
-int parse_impl(const uint8_t* x, uint64_t n, const lz_params& pr, Parse& out) {
+int parse_impl(const uint8_t* x, uint64_t n, const lz_params& pr, unsigned threads, Parse& out) {
   const uint32_t bl = pr.block_log2;
   const uint64_t B = 1ull << bl, nb = (n + B - 1) >> bl;
   const uint32_t h = pr.hash_len, m = pr.min_match, D = pr.max_level;
@@ -97,13 +100,23 @@ int parse_impl(const uint8_t* x, uint64_t n, const lz_params& pr, Parse& out) {
   const uint64_t win = pr.window_log2 ? (1ull << pr.window_log2) : ~0ull;
   const int64_t beta = pr.level_penalty;
   const Pos kNone = (Pos)~(Pos)0;
-  Hasher hash(h, pr.hash_bits);
-  std::vector<Pos> head(1ull << pr.hash_bits, kNone), anchor(1ull << pr.hash_bits, kNone);
+  const Hasher hash(h, pr.hash_bits);
+  // hash of every insertable position, computed in parallel chunks
+  const uint64_t nh = n >= h ? n - h + 1 : 0;
+  std::vector<uint32_t> hv(nh ? nh : 1);
+  const uint64_t chunk = 1 << 20;
+  parallel_for((nh + chunk - 1) / chunk, threads, [&](uint64_t c, unsigned) {
+    const uint64_t e = std::min(nh, (c + 1) * chunk);
+    for (uint64_t p = c * chunk; p < e; p++) hv[p] = (uint32_t)hash(x, p, n);
+  });
+  // head and anchor of a hash share one 2-entry slot (one cache line)
+  std::vector<Pos> ha(2ull << pr.hash_bits, kNone);
   // prev link of position q lives at q & ring_mask (a full array without a window)
   uint64_t ring = n;
   if (pr.window_log2 && (1ull << pr.window_log2) < n) ring = 1ull << pr.window_log2;
   const uint64_t ring_mask = (ring == n) ? ~0ull : ring - 1;
   std::vector<Pos> prev(ring ? ring : 1, kNone);
+  constexpr uint64_t kAhead = 24;
 
   out.seq_ptr.assign(nb + 1, 0);
   out.level.assign(nb, 0);
@@ -117,18 +130,19 @@ int parse_impl(const uint8_t* x, uint64_t n, const lz_params& pr, Parse& out) {
     uint32_t blevel = 0;
     while (p < eb) {
       for (; ins < p; ins++) {
-        if (ins + h > n) continue;
-        uint64_t hv = hash(x, ins, n);
-        prev[ins & ring_mask] = head[hv];
-        head[hv] = (Pos)ins;
-        if (anchor[hv] == kNone) anchor[hv] = (Pos)ins;
+        if (ins >= nh) continue;
+        if (ins + kAhead < nh) __builtin_prefetch(&ha[2ull * hv[ins + kAhead]], 1, 1);
+        Pos* slot = &ha[2ull * hv[ins]];
+        prev[ins & ring_mask] = slot[0];
+        slot[0] = (Pos)ins;
+        if (slot[1] == kNone) slot[1] = (Pos)ins;
       }
       uint64_t bestL = 0, bestQ = 0;
       uint32_t bestLv = 0;
       int64_t bestSc = 0;
       if (p + m <= eb) {
-        const uint64_t hv = hash(x, p, n);
-        const Pos a = anchor[hv];
+        const Pos* slot = &ha[2ull * hv[p]];
+        const Pos a = slot[1];
         bool anchor_seen = false;
         auto consider = [&](uint64_t q) {
           uint64_t L = lcp(x, q, p, eb - p);
@@ -150,7 +164,7 @@ int parse_impl(const uint8_t* x, uint64_t n, const lz_params& pr, Parse& out) {
             bestLv = lv;
           }
         };
-        Pos q = head[hv];
+        Pos q = slot[0];
         uint64_t cnt = 0;
         while (q != kNone && cnt < C && p - (uint64_t)q <= win) {
           if (q == a) anchor_seen = true;
@@ -413,7 +427,7 @@ extern "C" int lz_encode(const uint8_t* x, uint64_t n, const lz_params* pp, uint
     }
   }
   Parse ps;
-  int rc = n < (1ull << 32) - 1 ? parse_impl<uint32_t>(x, n, pr, ps) : parse_impl<uint64_t>(x, n, pr, ps);
+  int rc = n < (1ull << 32) - 1 ? parse_impl<uint32_t>(x, n, pr, threads, ps) : parse_impl<uint64_t>(x, n, pr, threads, ps);
   if (rc) return lz_fail(rc, "lz_encode: parse failed");
 
   // per-block stream bytes, built on demand

@@ -29,44 +29,37 @@ constexpr int kWG = 256;
 constexpr int kWaves = kWG / 64;
 constexpr uint32_t kB = 1u << kMaxBlockLog2;      // largest block: 16 KiB tile
 constexpr uint32_t kMaxSeq = 1025;                // B/m + 1 for B = 16 KiB, m = 16
-constexpr uint32_t kLutLit = 1u << kMaxPLit;      // 4096 entries
-constexpr uint32_t kLutSeq = 1u << kMaxPSeq;      // 1024 entries per small table
-constexpr uint32_t kLutWords = kLutLit + 3 * kLutSeq;
-constexpr uint32_t kStage = kB;                   // staging bytes (rANS bodies)
+constexpr uint32_t kLutLit = 1u << kMaxPLit;      // 4096 packed literal entries
+constexpr uint32_t kStage = kB;                   // staging bytes for rANS bodies
 constexpr uint32_t kL = 1u << 16;                 // rANS state lower bound
 
-__device__ __forceinline__ uint32_t lut_base(int kind) {
-  return kind == kLit ? 0u : kLutLit + (uint32_t)(kind - 1) * kLutSeq;
-}
-
+// All LDS is static (about 61 KB): literal LUT, output tile, body staging,
+// small-stream cumulative tables, per-sequence tables.
 struct Smem {
-  uint32_t lut[kLutWords];
+  uint32_t lut[kLutLit];
   uint8_t tile[kB];
   alignas(16) uint8_t stage[kStage];
-  uint64_t of[kMaxSeq];
-  uint16_t ll[kMaxSeq + 1];
-  uint16_t ml[kMaxSeq + 1];
-  uint16_t lit[kMaxSeq + 1];   // exclusive scan of LL; [ns] = n_lit
-  uint16_t out[kMaxSeq + 1];   // exclusive scan of LL + ML; [ns] = block length
+  uint16_t cum[3][257];        // CMD, MLEN, OFF cumulative frequencies
+  uint16_t lit[kMaxSeq + 1];   // LL values, then exclusive scan of LL ([ns] = n_lit)
+  uint16_t out[kMaxSeq + 1];   // ML values, then exclusive scan of LL+ML ([ns] = block length)
+  uint32_t oflo[kMaxSeq];      // absolute source offsets, low 32 bits
+  uint8_t ofhi[kMaxSeq + 3];   // bits 32..39
+  uint16_t intl[kMaxSeq];      // matches whose source touches the block itself
   uint32_t scan[kWaves];
-  uint32_t hdr[4][6];          // per stream: mode, csym, K, n, nw, body_len
-  uint32_t body_off[4];        // byte offset of each body inside the block payload
   uint32_t item, err, nint;
-  uint16_t intl[kMaxSeq];      // indices of in-block / mixed-source matches
 };
 
 struct DevArgs {
   const uint8_t* arc;
-  uint64_t n, off_dir, off_dep_ptr, off_dep_idx, off_payload;
+  uint64_t n, off_tables, off_dir, off_dep_ptr, off_dep_idx, off_payload;
   uint32_t bl, w, m, lit_lanes, seq_lanes;
   uint32_t P[4];
-  const uint32_t* lut;      // workspace LUT images
+  const uint32_t* lut;      // workspace literal LUT image
   const uint32_t* queue;    // block ids in level order
-  const uint32_t* qptr;     // device count / offsets (see launch)
-  uint32_t q_begin, q_end;  // static slice (per-level launch) when qcount == null
-  const uint32_t* qcount;   // device-side queue length (request mode) or null
+  const uint32_t* qptr;     // request mode: device slice bounds (q_begin/q_end index it)
+  uint32_t q_begin, q_end;  // static slice of the queue
   uint8_t* out;             // whole-file output base (direct mode)
-  const uint64_t* addr;     // per-block device address (request mode) or null
+  const uint64_t* addr;     // request mode: per-block device address, or null
   uint32_t* flags;
   uint32_t* ctl;
   uint32_t persistent;
@@ -90,14 +83,60 @@ __device__ __forceinline__ void latch(uint32_t* ctl, uint32_t bits) {
   __hip_atomic_fetch_or(ctl + kCtlStatus, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Decode the symbols of one 64-lane group g of a rANS stream (one wave).
-// body: LDS copy of the record body (states, group word counts, words).
-// Returns true if the group ends with every state at 2^16 and every word read.
-template <class Out>
-__device__ bool rans_group(const uint8_t* body, uint32_t K, uint32_t n, uint32_t g,
-                           const uint32_t* lut, uint32_t P, Out&& out) {
+// One stream record, parsed by every thread from global memory (uniform).
+struct Stream {
+  uint32_t mode, csym, K, n, nw, blen, body;
+};
+
+// Parse and check the record at *off of a block payload; advances *off.
+__device__ __forceinline__ bool parse_stream(const uint8_t* pay, uint32_t plen, uint32_t* off,
+                                             uint32_t want, uint32_t maxK, Stream& s) {
+  if (*off + 16 > plen) return false;
+  const uint8_t* h = pay + *off;
+  s.mode = h[0];
+  s.csym = h[1];
+  s.K = (uint32_t)h[2] | ((uint32_t)h[3] << 8);
+  s.n = ld32(h + 4);
+  s.nw = ld32(h + 8);
+  s.blen = ld32(h + 12);
+  s.body = *off + 16;
+  if (s.n != want) return false;
+  switch (s.mode) {
+    case kModeEmpty: if (s.n || s.blen) return false; break;
+    case kModeConst: if (!s.n || s.blen) return false; break;
+    case kModeRaw: if (s.blen != s.n || s.body + s.blen > plen) return false; break;
+    case kModeRans: {
+      const uint32_t G = (s.K + 63) >> 6;
+      if (s.K < 1 || s.K > maxK || !s.n || s.body + s.blen > plen) return false;
+      if ((uint64_t)s.blen != 4ull * s.K + 4ull * G + 2ull * s.nw || s.blen > kStage) return false;
+      uint64_t sum = 0;
+      for (uint32_t g = 0; g < G; g++) sum += ld32(pay + s.body + 4 * s.K + 4 * g);
+      if (sum != s.nw) return false;
+      break;
+    }
+    default: return false;
+  }
+  *off = s.body + ((s.blen + 15u) & ~15u);
+  return true;
+}
+
+// Copy a rANS body to LDS staging at byte offset `at` (16-byte granules).
+__device__ __forceinline__ void stage_body(Smem& S, const uint8_t* pay, const Stream& s, uint32_t at) {
+  if (s.mode != kModeRans) return;
+  const uint4* src = reinterpret_cast<const uint4*>(pay + s.body);
+  uint4* dst = reinterpret_cast<uint4*>(S.stage + at);
+  const uint32_t n16 = (s.blen + 15u) >> 4;
+  for (uint32_t c = threadIdx.x; c < n16; c += kWG) dst[c] = src[c];
+}
+
+// Decode the symbols of 64-lane group g of a rANS stream with one wave.
+// `sym(x)` maps the state's slot to (symbol, f, slot - c) and `out(i, s)`
+// consumes symbol i.  True if every state ends at 2^16 and every word was read.
+template <class Sym, class Out>
+__device__ bool rans_group(const uint8_t* body, const Stream& s, uint32_t g, uint32_t P,
+                           Sym&& sym, Out&& out) {
   const uint32_t lane = lane_id();
-  const uint32_t G = (K + 63) >> 6;
+  const uint32_t K = s.K, n = s.n, G = (K + 63) >> 6;
   const uint32_t k = (g << 6) + lane;
   const bool lane_ok = k < K;
   const uint32_t* st = reinterpret_cast<const uint32_t*>(body);
@@ -107,7 +146,7 @@ __device__ bool rans_group(const uint8_t* body, uint32_t K, uint32_t n, uint32_t
   const uint32_t nwg = gw[g];
   const uint16_t* W = reinterpret_cast<const uint16_t*>(gw + G) + woff;
   uint32_t x = lane_ok ? st[k] : kL;
-  bool ok = x >= kL;
+  bool ok = x >= kL && woff + nwg <= s.nw;
   uint32_t pos = 0;
   const uint32_t rounds = (n + K - 1) / K;
   const uint32_t mask = (1u << P) - 1;
@@ -115,7 +154,7 @@ __device__ bool rans_group(const uint8_t* body, uint32_t K, uint32_t n, uint32_t
   for (uint32_t r = 0; r < rounds; r++, i += K) {
     const bool act = lane_ok && i < n;
     if (act) {
-      const uint32_t e = lut[x & mask];
+      const uint32_t e = sym(x & mask);          // symbol | f << 8 | bias << 20
       x = __umul24((e >> 8) & 0xFFFu, x >> P) + (e >> 20);
       out(i, e & 0xFFu);
     }
@@ -133,7 +172,7 @@ __device__ bool rans_group(const uint8_t* body, uint32_t K, uint32_t n, uint32_t
   return __ballot(!ok) == 0;
 }
 
-// Source byte at absolute position a for a match copy: direct mode reads the
+// Source byte at absolute position a (an earlier block): direct mode reads the
 // whole-file output; request mode goes through the per-block address table.
 __device__ __forceinline__ uint32_t src_byte(const DevArgs& A, uint64_t a, bool& bad) {
   if (!A.addr) return A.out[a];
@@ -142,8 +181,7 @@ __device__ __forceinline__ uint32_t src_byte(const DevArgs& A, uint64_t a, bool&
   return reinterpret_cast<const uint8_t*>(base)[a & ((1ull << A.bl) - 1)];
 }
 
-// Block-wide exclusive scan of v (one value per thread); returns the prefix
-// and writes the total to *total.
+// Block-wide exclusive scan of v; *total receives the sum.
 __device__ uint32_t block_scan(Smem& S, uint32_t v, uint32_t* total) {
   const uint32_t t = threadIdx.x, lane = lane_id(), wv = t >> 6;
   uint32_t incl = v;
@@ -155,7 +193,7 @@ __device__ uint32_t block_scan(Smem& S, uint32_t v, uint32_t* total) {
   __syncthreads();
   uint32_t base = 0, tot = 0;
   for (int q = 0; q < kWaves; q++) {
-    uint32_t s = S.scan[q];
+    const uint32_t s = S.scan[q];
     if (q < (int)wv) base += s;
     tot += s;
   }
@@ -164,65 +202,19 @@ __device__ uint32_t block_scan(Smem& S, uint32_t v, uint32_t* total) {
   return base + incl - v;
 }
 
-// Parse the 4 stream records of a block; fills S.hdr / S.body_off.  Thread 0.
-__device__ bool parse_streams(Smem& S, const uint8_t* pay, uint32_t plen, uint32_t ns,
-                              uint32_t nlit, const DevArgs& A) {
-  static constexpr int order[4] = {kCmd, kMlen, kOff, kLit};
-  uint32_t off = 0;
-  for (int q = 0; q < 4; q++) {
-    const int kind = order[q];
-    if (off + 16 > plen) return false;
-    const uint8_t* h = pay + off;
-    const uint32_t mode = h[0], csym = h[1], K = (uint32_t)h[2] | ((uint32_t)h[3] << 8);
-    const uint32_t n = ld32(h + 4), nw = ld32(h + 8), bl = ld32(h + 12);
-    const uint32_t want = kind == kLit ? nlit : (kind == kOff ? A.w * ns : 2 * ns);
-    if (n != want) return false;
-    const uint32_t body = off + 16;
-    const uint32_t maxK = kind == kLit ? A.lit_lanes : A.seq_lanes;
-    switch (mode) {
-      case kModeEmpty: if (n != 0 || bl != 0) return false; break;
-      case kModeConst: if (n == 0 || bl != 0) return false; break;
-      case kModeRaw: if (bl != n || body + bl > plen) return false; break;
-      case kModeRans: {
-        const uint32_t G = (K + 63) >> 6;
-        if (K < 1 || K > maxK || n == 0 || body + bl > plen) return false;
-        if ((uint64_t)bl != 4ull * K + 4ull * G + 2ull * nw) return false;
-        if (bl > kStage) return false;
-        uint64_t sum = 0;     // per-group word counts must add up to n_words
-        for (uint32_t g = 0; g < G; g++) sum += ld32(pay + body + 4 * K + 4 * g);
-        if (sum != nw) return false;
-        break;
-      }
-      default: return false;
-    }
-    uint32_t* hd = S.hdr[kind];
-    hd[0] = mode; hd[1] = csym; hd[2] = K; hd[3] = n; hd[4] = nw; hd[5] = bl;
-    S.body_off[kind] = body;
-    off = body + ((bl + 15u) & ~15u);
-  }
-  return true;
+// Small-stream symbol lookup: binary search of slot u in a 257-entry
+// cumulative table; returns symbol | f << 8 | (u - c_s) << 20.
+__device__ __forceinline__ uint32_t search_sym(const uint16_t* cum, uint32_t u) {
+  uint32_t lo = 0;
+#pragma unroll
+  for (uint32_t step = 128; step; step >>= 1)
+    if (cum[lo + step] <= u) lo += step;
+  const uint32_t c = cum[lo], f = cum[lo + 1] - c;
+  return lo | ((f & 0xFFFu) << 8) | ((u - c) << 20);
 }
 
-// Copy rANS bodies of the given kinds from global to consecutive 16-byte
-// aligned LDS staging offsets; returns the staging offset of each.
-__device__ void stage_bodies(Smem& S, const uint8_t* pay, const int* kinds, int nk, uint32_t* soff) {
-  uint32_t o = 0;
-  for (int q = 0; q < nk; q++) {
-    soff[q] = o;
-    if (S.hdr[kinds[q]][0] == kModeRans) o += (S.hdr[kinds[q]][5] + 15u) & ~15u;
-  }
-  for (int q = 0; q < nk; q++) {
-    const int kind = kinds[q];
-    if (S.hdr[kind][0] != kModeRans) continue;
-    const uint32_t bl = S.hdr[kind][5];
-    const uint4* src = reinterpret_cast<const uint4*>(pay + S.body_off[kind]);
-    uint4* dst = reinterpret_cast<uint4*>(S.stage + soff[q]);
-    for (uint32_t c = threadIdx.x; c < (bl + 15u) >> 4; c += kWG) dst[c] = src[c];
-  }
-}
-
-// Decode one whole block b into the LDS tile and store it; returns false on a
-// corrupt block (status already latched).
+// Decode block b into the LDS tile and store it.  Every loop below is bounded
+// by values read from global memory (directory, stream headers).
 __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
   const uint32_t t = threadIdx.x, wv = t >> 6, lane = lane_id();
   const uint64_t B = 1ull << A.bl;
@@ -233,126 +225,157 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
   const uint32_t plen = ld32(de + 8), ns = ld32(de + 12), nlit = ld32(de + 16);
   const uint8_t* pay = A.arc + A.off_payload + poff;
 
-  if (t == 0) {
-    bool ok = ns >= 1 && ns <= kMaxSeq && nlit <= blen && ((poff & 15) == 0);
-    ok = ok && parse_streams(S, pay, plen, ns, nlit, A);
-    S.err = ok ? 0u : 1u;
+  // stream records: CMD, MLEN, OFF, LIT (every thread parses the same bytes)
+  Stream sc, sm, so, sl;
+  uint32_t off = 0;
+  bool ok = ns >= 1 && ns <= kMaxSeq && nlit <= blen && (poff & 15) == 0;
+  ok = ok && parse_stream(pay, plen, &off, 2 * ns, A.seq_lanes, sc);
+  ok = ok && parse_stream(pay, plen, &off, 2 * ns, A.seq_lanes, sm);
+  ok = ok && parse_stream(pay, plen, &off, A.w * ns, A.seq_lanes, so);
+  ok = ok && parse_stream(pay, plen, &off, nlit, A.lit_lanes, sl);
+  if (!ok) {
+    if (t == 0) latch(A.ctl, kStCorrupt);
+    return;
   }
-  __syncthreads();
-  if (S.err) { if (t == 0) latch(A.ctl, kStCorrupt); return; }
+  const uint32_t a_cmd = 0;
+  const uint32_t a_mln = a_cmd + (sc.mode == kModeRans ? ((sc.blen + 15u) & ~15u) : 0u);
+  const uint32_t a_off = a_mln + (sm.mode == kModeRans ? ((sm.blen + 15u) & ~15u) : 0u);
+  const uint32_t small_end = a_off + (so.mode == kModeRans ? ((so.blen + 15u) & ~15u) : 0u);
+  if (small_end > kStage) {
+    if (t == 0) latch(A.ctl, kStCorrupt);
+    return;
+  }
 
-  // ---- stage 1: small streams
-  static constexpr int small[3] = {kCmd, kMlen, kOff};
-  uint32_t soff[3];
-  stage_bodies(S, pay, small, 3, soff);
-  for (uint32_t j = t; j < ns; j += kWG) S.of[j] = 0;
+  // ---- stage 1: CMD -> lit[] (LL), MLEN -> out[] (ML), OFF -> oflo/ofhi
+  stage_body(S, pay, sc, a_cmd);
+  stage_body(S, pay, sm, a_mln);
+  stage_body(S, pay, so, a_off);
+  for (uint32_t j = t; j < ns; j += kWG) { S.oflo[j] = 0; S.ofhi[j] = 0; }
+  if (t == 0) { S.err = 0; S.nint = 0; }
   __syncthreads();
-  bool ok = true;
   if (wv < 3) {
-    const int kind = small[wv];
-    const uint32_t* hd = S.hdr[kind];
-    const uint32_t mode = hd[0], n = hd[3];
-    uint8_t* dstb = kind == kCmd ? reinterpret_cast<uint8_t*>(S.ll)
-                  : kind == kMlen ? reinterpret_cast<uint8_t*>(S.ml)
-                                  : reinterpret_cast<uint8_t*>(S.of);
-    const uint32_t stride = kind == kOff ? 8u : 2u;
-    auto put = [&](uint32_t i, uint32_t s) {
+    const Stream& s = wv == 0 ? sc : (wv == 1 ? sm : so);
+    const uint32_t at = wv == 0 ? a_cmd : (wv == 1 ? a_mln : a_off);
+    const uint16_t* cum = S.cum[wv];
+    uint8_t* dst8 = wv == 0 ? reinterpret_cast<uint8_t*>(S.lit) : reinterpret_cast<uint8_t*>(S.out);
+    auto put = [&](uint32_t i, uint32_t v) {
       uint32_t plane = 0, idx = i;
-      while (idx >= ns) { idx -= ns; plane++; }
-      dstb[idx * stride + plane] = (uint8_t)s;
+      while (idx >= ns && plane < 7) { idx -= ns; plane++; }
+      if (wv < 2) {
+        dst8[2 * idx + plane] = (uint8_t)v;
+      } else if (plane < 4) {
+        reinterpret_cast<uint8_t*>(S.oflo)[4 * idx + plane] = (uint8_t)v;
+      } else {
+        S.ofhi[idx] = (uint8_t)v;
+      }
     };
-    if (mode == kModeRans) {
-      ok = rans_group(S.stage + soff[wv], hd[2], n, 0, S.lut + lut_base(kind), A.P[kind], put);
-    } else if (mode == kModeRaw) {
-      const uint8_t* src = pay + S.body_off[kind];
-      for (uint32_t i = lane; i < n; i += 64) put(i, src[i]);
-    } else if (mode == kModeConst) {
-      for (uint32_t i = lane; i < n; i += 64) put(i, hd[1]);
+    bool okw = true;
+    if (s.mode == kModeRans) {
+      okw = rans_group(S.stage + at, s, 0, A.P[1 + wv],
+                       [&](uint32_t u) { return search_sym(cum, u); }, put);
+    } else if (s.mode == kModeRaw) {
+      const uint8_t* src = pay + s.body;
+      for (uint32_t i = lane; i < s.n; i += 64) put(i, src[i]);
+    } else if (s.mode == kModeConst) {
+      for (uint32_t i = lane; i < s.n; i += 64) put(i, s.csym);
     }
+    if (!okw && lane == 0) S.err = 1;
   }
-  if (!ok && lane == 0) S.err = 1;
   __syncthreads();
-  if (S.err) { if (t == 0) latch(A.ctl, kStCorrupt); return; }
 
-  // ---- stage 2: command placement (exclusive scans of LL and LL + ML)
+  // ---- stage 2: command placement; in-place exclusive scans of LL and LL+ML
   {
     const uint32_t per = (ns + kWG - 1) / kWG;
-    const uint32_t j0 = t * per, j1 = min(ns, j0 + per);
-    uint32_t sl = 0, so = 0;
-    for (uint32_t j = j0; j < j1; j++) { sl += S.ll[j]; so += S.ll[j] + S.ml[j]; }
-    uint32_t tl, to;
-    uint32_t bl_ = block_scan(S, sl, &tl);
-    uint32_t bo = block_scan(S, so, &to);
-    bool bad = false;
-    for (uint32_t j = j0; j < j1; j++) {
-      S.lit[j] = (uint16_t)bl_;
-      S.out[j] = (uint16_t)bo;
-      const uint32_t L = S.ll[j], M = S.ml[j];
-      const uint64_t of = S.of[j];
-      const uint64_t dst = sb + bo + L;
-      if (M == 0) bad |= (j != ns - 1) || of != 0;
-      else bad |= M < A.m || of >= dst;
-      bl_ += L;
-      bo += L + M;
+    const uint32_t j0 = min(ns, t * per), j1 = min(ns, j0 + per);
+    uint32_t ll[5], ml[5];
+    uint32_t sl_ = 0, so_ = 0;
+    for (uint32_t j = j0, q = 0; j < j1; j++, q++) {
+      ll[q] = S.lit[j];
+      ml[q] = S.out[j];
+      sl_ += ll[q];
+      so_ += ll[q] + ml[q];
     }
-    if (t == 0) { S.lit[ns] = (uint16_t)min(tl, 65535u); S.out[ns] = (uint16_t)min(to, 65535u); }
-    if (tl != nlit || to != blen) bad = true;
+    uint32_t tl, to;
+    uint32_t pl = block_scan(S, sl_, &tl);
+    uint32_t po = block_scan(S, so_, &to);
+    bool bad = tl != nlit || to != blen;
+    for (uint32_t j = j0, q = 0; j < j1; j++, q++) {
+      S.lit[j] = (uint16_t)pl;
+      S.out[j] = (uint16_t)po;
+      const uint64_t of = (uint64_t)S.oflo[j] | ((uint64_t)S.ofhi[j] << 32);
+      if (ml[q] == 0) bad |= (j != ns - 1) || of != 0;
+      else bad |= ml[q] < A.m || of >= sb + po + ll[q];
+      pl += ll[q];
+      po += ll[q] + ml[q];
+    }
+    if (t == 0) {
+      S.lit[ns] = (uint16_t)min(tl, 65535u);
+      S.out[ns] = (uint16_t)min(to, 65535u);
+    }
     if (bad) S.err = 1;
-    if (t == 0) S.nint = 0;
   }
   __syncthreads();
-  if (S.err) { if (t == 0) latch(A.ctl, kStCorrupt); return; }
+  if (S.err) {
+    if (t == 0) latch(A.ctl, kStCorrupt);
+    return;
+  }
 
-  // ---- stage 3: literals straight into the tile
+  // ---- stage 3: literals straight to their tile positions; external matches
+  stage_body(S, pay, sl, 0);
+  __syncthreads();
   {
-    static constexpr int litk[1] = {kLit};
-    const uint32_t* hd = S.hdr[kLit];
-    const uint32_t mode = hd[0], n = hd[3];
-    uint32_t so1[1];
-    stage_bodies(S, pay, litk, 1, so1);
-    __syncthreads();
-    uint32_t j = 0;   // per-lane current sequence (monotone in i)
-    auto place = [&](uint32_t i, uint32_t s) {
-      while (i >= S.lit[j + 1]) j++;
-      S.tile[S.out[j] + (i - S.lit[j])] = (uint8_t)s;
-    };
-    bool okl = true;
-    if (mode == kModeRans) {
-      const uint32_t G = (hd[2] + 63) >> 6;
-      for (uint32_t g = wv; g < G; g += kWaves)
-        okl = okl && rans_group(S.stage, hd[2], n, g, S.lut + lut_base(kLit), A.P[kLit], place);
-    } else if (mode == kModeRaw) {
-      const uint8_t* src = pay + S.body_off[kLit];
-      for (uint32_t i = t; i < n; i += kWG) place(i, src[i]);
-    } else if (mode == kModeConst) {
-      for (uint32_t i = t; i < n; i += kWG) place(i, hd[1]);
-    }
-    if (!okl && lane == 0) S.err = 1;
-    // classify matches: wholly external ones are copied now, in parallel
     bool bad = false;
+    uint32_t j = 0;                            // per-lane sequence cursor
+    uint32_t nxt = S.lit[1], dlt = S.out[0] - S.lit[0];
+    auto place = [&](uint32_t i, uint32_t v) {
+      while (i >= nxt && j + 1 < ns) {
+        j++;
+        nxt = S.lit[j + 1];
+        dlt = (uint32_t)S.out[j] - (uint32_t)S.lit[j];
+      }
+      const uint32_t a = i + dlt;
+      if (a < blen) S.tile[a] = (uint8_t)v;
+    };
+    if (sl.mode == kModeRans) {
+      const uint32_t G = (sl.K + 63) >> 6;
+      for (uint32_t g = wv; g < G; g += kWaves)
+        if (!rans_group(S.stage, sl, g, A.P[kLit], [&](uint32_t u) { return S.lut[u]; }, place)) bad = true;
+    } else if (sl.mode == kModeRaw) {
+      const uint8_t* src = pay + sl.body;
+      for (uint32_t i = t; i < sl.n; i += kWG) place(i, src[i]);
+    } else if (sl.mode == kModeConst) {
+      for (uint32_t i = t; i < sl.n; i += kWG) place(i, sl.csym);
+    }
+    // matches with a source wholly in earlier blocks: copy now, in parallel
     for (uint32_t q = wv; q < ns; q += kWaves) {
-      const uint32_t M = S.ml[q];
+      const uint32_t L = (uint32_t)S.lit[q + 1] - S.lit[q];
+      const uint32_t M = (uint32_t)S.out[q + 1] - S.out[q] - L;
       if (!M) continue;
-      const uint64_t of = S.of[q];
+      const uint64_t of = (uint64_t)S.oflo[q] | ((uint64_t)S.ofhi[q] << 32);
+      const uint32_t d0 = S.out[q] + L;
       if (of + M <= sb) {
-        const uint32_t d0 = S.out[q] + S.ll[q];
-        for (uint32_t k = lane; k < M; k += 64) S.tile[d0 + k] = (uint8_t)src_byte(A, of + k, bad);
+        for (uint32_t k = lane; k < M && d0 + k < blen; k += 64) S.tile[d0 + k] = (uint8_t)src_byte(A, of + k, bad);
       } else if (lane == 0) {
-        S.intl[atomicAdd(&S.nint, 1u)] = q;
+        const uint32_t slot = atomicAdd(&S.nint, 1u);
+        if (slot < kMaxSeq) S.intl[slot] = (uint16_t)q;
       }
     }
     if (bad) S.err = 1;
   }
   __syncthreads();
-  if (S.err) { if (t == 0) latch(A.ctl, kStCorrupt); return; }
+  if (S.err) {
+    if (t == 0) latch(A.ctl, kStCorrupt);
+    return;
+  }
 
-  // ---- stage 4: in-block / mixed-source matches in sequence order (wave 0)
-  if (wv == 0 && S.nint) {
-    // order the (few) collected matches by sequence index: insertion sort
-    const uint32_t cnt = S.nint;
+  // ---- stage 4: matches touching the block itself, in sequence order (wave 0),
+  // min(period, 64) bytes per step: out[p+k] = out[OF+k] byte-sequentially
+  if (wv == 0) {
+    const uint32_t cnt = min(S.nint, ns);
     if (lane == 0)
       for (uint32_t a = 1; a < cnt; a++) {
-        uint32_t v = S.intl[a], c = a;
+        const uint16_t v = S.intl[a];
+        uint32_t c = a;
         while (c > 0 && S.intl[c - 1] > v) { S.intl[c] = S.intl[c - 1]; c--; }
         S.intl[c] = v;
       }
@@ -360,29 +383,33 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
     __builtin_amdgcn_wave_barrier();
     bool bad = false;
     for (uint32_t a = 0; a < cnt; a++) {
-      const uint32_t q = S.intl[a];
-      const uint32_t M = S.ml[q];
-      const uint32_t d0 = S.out[q] + S.ll[q];
-      const uint64_t of = S.of[q];
+      const uint32_t q = min((uint32_t)S.intl[a], ns - 1);
+      const uint32_t L = (uint32_t)S.lit[q + 1] - S.lit[q];
+      const uint32_t M = min((uint32_t)S.out[q + 1] - S.out[q] - L, blen);
+      const uint32_t d0 = S.out[q] + L;
+      const uint64_t of = (uint64_t)S.oflo[q] | ((uint64_t)S.ofhi[q] << 32);
       const uint64_t dabs = sb + d0;
-      const uint32_t step = (dabs - of) < 64 ? (uint32_t)(dabs - of) : 64u;
+      const uint32_t step = dabs > of ? (dabs - of < 64 ? (uint32_t)(dabs - of) : 64u) : 1u;
       for (uint32_t c = 0; c < M; c += step) {
         const uint32_t k = c + lane;
-        if (lane < step && k < M) {
+        if (lane < step && k < M && d0 + k < blen) {
           const uint64_t s = of + k;
-          const uint32_t v = s >= sb ? (uint32_t)S.tile[s - sb] : src_byte(A, s, bad);
+          const uint32_t v = s >= sb ? (uint32_t)S.tile[(uint32_t)(s - sb) & (kB - 1)] : src_byte(A, s, bad);
           S.tile[d0 + k] = (uint8_t)v;
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
       }
     }
-    if (bad) S.err = 1;
+    if (bad && lane == 0) S.err = 1;
   }
   __syncthreads();
-  if (S.err) { if (t == 0) latch(A.ctl, kStCorrupt); return; }
+  if (S.err) {
+    if (t == 0) latch(A.ctl, kStCorrupt);
+    return;
+  }
 
-  // ---- stage 5: tile -> HBM, 16-byte stores
+  // ---- stage 5: tile -> HBM with 16-byte stores
   uint8_t* dst = A.addr ? reinterpret_cast<uint8_t*>(A.addr[b]) : A.out + sb;
   if (dst) {
     const uint32_t full = blen >> 4;
@@ -393,21 +420,42 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
   }
 }
 
-__device__ void load_luts(Smem& S, const uint32_t* lut) {
-  const uint4* s = reinterpret_cast<const uint4*>(lut);
+// Once per workgroup: literal LUT image into LDS, small-stream cumulative tables.
+__device__ void load_tables(Smem& S, const DevArgs& A) {
+  const uint4* s = reinterpret_cast<const uint4*>(A.lut);
   uint4* d = reinterpret_cast<uint4*>(S.lut);
-  for (uint32_t c = threadIdx.x; c < kLutWords / 4; c += kWG) d[c] = s[c];
+  for (uint32_t c = threadIdx.x; c < kLutLit / 4; c += kWG) d[c] = s[c];
+  const uint32_t t = threadIdx.x;
+  if (t < 3 * 64) {          // waves 0..2: one table each, 4 symbols per lane
+    const uint32_t k = t >> 6, lane = t & 63;
+    const uint8_t* tab = A.arc + A.off_tables + 512 * (k + 1);
+    uint32_t f[4], sum = 0;
+    for (int q = 0; q < 4; q++) {
+      f[q] = (uint32_t)tab[2 * (4 * lane + q)] | ((uint32_t)tab[2 * (4 * lane + q) + 1] << 8);
+      sum += f[q];
+    }
+    uint32_t incl = sum;
+    for (int d = 1; d < 64; d <<= 1) {
+      uint32_t y = __shfl_up(incl, d, 64);
+      if (lane >= (uint32_t)d) incl += y;
+    }
+    uint32_t c = incl - sum;
+    for (int q = 0; q < 4; q++) {
+      S.cum[k][4 * lane + q] = (uint16_t)c;
+      c += f[q];
+    }
+    if (lane == 63) S.cum[k][256] = (uint16_t)min(c, 65535u);
+  }
 }
 
 __global__ void __launch_bounds__(kWG) k_decode(DevArgs A) {
-  extern __shared__ __align__(16) uint8_t smem_raw[];
-  Smem& S = *reinterpret_cast<Smem*>(smem_raw);
+  __shared__ Smem S;
   const uint32_t t = threadIdx.x;
-  load_luts(S, A.lut);
+  load_tables(S, A);
   __syncthreads();
   const uint32_t epoch = __hip_atomic_load(A.ctl + kCtlEpoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   uint32_t qb = A.q_begin, qe = A.q_end;
-  if (A.qptr) {            // request mode: slice bounds read on the device
+  if (A.qptr) {
     qb = A.qptr[A.q_begin];
     qe = A.qptr[A.q_end];
   }
@@ -425,15 +473,15 @@ __global__ void __launch_bounds__(kWG) k_decode(DevArgs A) {
     __syncthreads();
     if (it >= qe) break;
     const uint32_t b = A.queue[it];
-    // wait for every dependency's completion flag (acquire)
+    // wait for every dependency's completion flag, then acquire
     const uint64_t d0 = ld64(A.arc + A.off_dep_ptr + 8ull * b);
     const uint64_t d1 = ld64(A.arc + A.off_dep_ptr + 8ull * (b + 1));
     for (uint64_t k = d0 + t; k < d1; k += kWG) {
       const uint32_t d = ld32(A.arc + A.off_dep_idx + 4 * k);
-      uint32_t spins = 0;
-      while (__hip_atomic_load(A.flags + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+      for (uint32_t spins = 0;
+           __hip_atomic_load(A.flags + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch; spins++) {
+        if (spins >= A.spin_limit) { latch(A.ctl, kStWatchdog); break; }
         __builtin_amdgcn_s_sleep(1);
-        if (++spins > A.spin_limit) { latch(A.ctl, kStWatchdog); break; }
       }
     }
     __syncthreads();
@@ -447,35 +495,25 @@ __global__ void __launch_bounds__(kWG) k_decode(DevArgs A) {
 
 // ---- setup kernels ---------------------------------------------------------
 
-// Packed decode entry of slot u: symbol | f << 8 | (u - c_s) << 20, for the
-// four tables (LIT with 2^P_LIT slots, the others with 2^P slots each).
-__global__ void k_build_lut(const uint8_t* arc, uint64_t off_tables, uint32_t p0, uint32_t p1,
-                            uint32_t p2, uint32_t p3, uint32_t* lut) {
+// Packed literal decode entry of slot u: symbol | f << 8 | (u - c_s) << 20.
+__global__ void k_build_lut(const uint8_t* arc, uint64_t off_tables, uint32_t P, uint32_t* lut) {
   __shared__ uint32_t cum[257];
   __shared__ uint32_t fr[256];
-  const int kind = blockIdx.x;
-  const uint32_t P = kind == 0 ? p0 : kind == 1 ? p1 : kind == 2 ? p2 : p3;
-  const uint8_t* tab = arc + off_tables + 512 * kind;
-  for (int s = threadIdx.x; s < 256; s += blockDim.x) fr[s] = (uint32_t)tab[2 * s] | ((uint32_t)tab[2 * s + 1] << 8);
+  for (int s = threadIdx.x; s < 256; s += blockDim.x)
+    fr[s] = (uint32_t)arc[off_tables + 2 * s] | ((uint32_t)arc[off_tables + 2 * s + 1] << 8);
   __syncthreads();
   if (threadIdx.x == 0) {
     cum[0] = 0;
     for (int s = 0; s < 256; s++) cum[s + 1] = cum[s] + fr[s];
   }
   __syncthreads();
-  uint32_t* out = lut + (kind == 0 ? 0u : kLutLit + (uint32_t)(kind - 1) * kLutSeq);
   const uint32_t M = 1u << P;
-  const uint32_t cap = kind == 0 ? kLutLit : kLutSeq;
-  if (cum[256] != M) {     // unused (all-zero) table
-    for (uint32_t u = threadIdx.x; u < cap; u += blockDim.x) out[u] = 0;
-    return;
-  }
-  for (uint32_t u = threadIdx.x; u < cap; u += blockDim.x) {
-    if (u >= M) { out[u] = 0; continue; }
-    uint32_t lo = 0, hi = 256;   // largest s with cum[s] <= u
-    while (hi - lo > 1) { uint32_t mid = (lo + hi) >> 1; if (cum[mid] <= u) lo = mid; else hi = mid; }
-    const uint32_t f = fr[lo];
-    out[u] = lo | ((f & 0xFFFu) << 8) | ((u - cum[lo]) << 20);
+  for (uint32_t u = threadIdx.x; u < kLutLit; u += blockDim.x) {
+    if (cum[256] != M || u >= M) { lut[u] = 0; continue; }
+    uint32_t lo = 0;
+    for (uint32_t step = 128; step; step >>= 1)
+      if (cum[lo + step] <= u) lo += step;
+    lut[u] = lo | ((fr[lo] & 0xFFFu) << 8) | ((u - cum[lo]) << 20);
   }
 }
 
@@ -504,6 +542,7 @@ static DevArgs make_args(const lz_handle* h) {
   const ArchiveView& v = h->av;
   A.arc = v.base;
   A.n = v.n;
+  A.off_tables = v.off_tables;
   A.off_dir = v.off_dir;
   A.off_dep_ptr = v.off_dep_ptr;
   A.off_dep_idx = v.off_dep_idx;
@@ -529,8 +568,7 @@ static int launch_ok(const char* what) {
 
 int lz_launch_setup(lz_handle* h, hipStream_t s) {
   const ArchiveView& v = h->av;
-  hipLaunchKernelGGL(k_build_lut, dim3(4), dim3(256), 0, s, v.base, v.off_tables, v.prob_bits[0],
-                     v.prob_bits[1], v.prob_bits[2], v.prob_bits[3], h->ws.lut);
+  hipLaunchKernelGGL(k_build_lut, dim3(1), dim3(256), 0, s, v.base, v.off_tables, v.prob_bits[0], h->ws.lut);
   const uint64_t nb = v.n_blocks;
   const uint32_t grid = (uint32_t)std::min<uint64_t>(4096, (nb + 255) / 256 + 1);
   hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(256), 0, s, h->ws.flags, nb, 0u);
@@ -544,7 +582,7 @@ int lz_launch_decode_all(lz_handle* h, uint8_t* out, hipStream_t s) {
   DevArgs A = make_args(h);
   A.queue = h->ws.queue;
   A.out = out;
-  const size_t smem = sizeof(Smem);
+  const size_t smem = 0;   // all LDS is static
   const uint32_t slots = (uint32_t)(h->n_cu * std::max(1u, h->tune.wg_per_cu));
   hipLaunchKernelGGL(k_begin, dim3(1), dim3(1), 0, s, h->ws.ctl);
   if (h->tune.sync_mode == 1) {

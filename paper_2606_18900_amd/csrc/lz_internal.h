@@ -19,7 +19,8 @@ enum StreamMode { kModeEmpty = 0, kModeConst = 1, kModeRaw = 2, kModeRans = 3 };
 // device limits of the decoder
 constexpr uint32_t kMaxBlockLog2 = 14;
 constexpr uint32_t kMaxPLit = 12;
-constexpr uint32_t kMaxPSeq = 10;
+constexpr uint32_t kMaxPSeq = 12;
+constexpr uint32_t kMaxOffsetWidth = 5;   // absolute offsets below 2^40
 constexpr uint32_t kMaxLevels = 64;
 
 // status bits latched by kernels in the workspace status word
@@ -45,7 +46,7 @@ struct ArchiveView {
 
 // Workspace carve-up (device pointers), see lz_open.
 struct Workspace {
-  uint32_t* lut;          // 4096 + 3*1024 packed decode entries
+  uint32_t* lut;          // 4096 packed literal decode entries
   uint32_t* queue;        // n_blocks: whole-file level-ordered block ids
   uint32_t* level_ptr;    // 65: level offsets into queue
   uint32_t* flags;        // n_blocks: completion epoch per block

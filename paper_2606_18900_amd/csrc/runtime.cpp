@@ -103,7 +103,7 @@ Layout layout_for(uint64_t nb) {
   Layout L{};
   uint64_t o = 0;
   auto take = [&](uint64_t bytes) { uint64_t r = o; o = (o + bytes + 255) & ~255ull; return r; };
-  L.lut = take((4096 + 3 * 1024) * 4);
+  L.lut = take(4096 * 4);
   L.queue = take(4 * std::max<uint64_t>(nb, 1));
   L.level_ptr = take(4 * 65);
   L.flags = take(4 * std::max<uint64_t>(nb, 1));
@@ -222,8 +222,7 @@ extern "C" int lz_open(const uint8_t* d_archive, uint64_t len, void* d_ws, uint6
   if (n_levels != v.n_levels) return lz_fail(LZ_EFORMAT, "n_levels mismatch");
   // device limits of this decoder
   if (v.block_log2 > kMaxBlockLog2) return lz_fail(LZ_EFORMAT, "device decoder supports blocks up to 16 KiB");
-  if (v.prob_bits[kLit] > kMaxPLit || v.prob_bits[kCmd] > kMaxPSeq || v.prob_bits[kMlen] > kMaxPSeq || v.prob_bits[kOff] > kMaxPSeq)
-    return lz_fail(LZ_EFORMAT, "device decoder supports P <= 12 (literals) and <= 10 (other streams)");
+  if (v.offset_width > kMaxOffsetWidth) return lz_fail(LZ_EFORMAT, "device decoder supports files below 2^40 bytes");
   if ((1ull << v.block_log2) / v.min_match + 1 > 1025) return lz_fail(LZ_EFORMAT, "device decoder supports at most 1025 sequences per block");
   if (v.kind == 1) {
     std::vector<uint64_t> idx(v.n_reads + 1);
@@ -266,11 +265,7 @@ extern "C" int lz_open(const uint8_t* d_archive, uint64_t len, void* d_ws, uint6
   if (!rc) rc = hip_check(hipGetDeviceProperties(&prop, dev), "lz_open: properties");
   if (rc) { delete h; return rc; }
   h->n_cu = prop.multiProcessorCount;
-  const size_t smem = lz_decode_smem_bytes();
-  if (smem > (size_t)prop.sharedMemPerBlock) {
-    delete h;
-    return lz_fail(LZ_EDEVICE, "decoder needs %zu bytes of LDS, device offers %zu", smem, (size_t)prop.sharedMemPerBlock);
-  }
+
   // level-ordered queue of the whole file (ascending block id inside a level)
   std::vector<uint32_t> lptr(65, 0), queue(std::max<uint64_t>(nb, 1));
   for (uint32_t k = 0; k < kMaxLevels; k++) lptr[k + 1] = lptr[k] + count[k];

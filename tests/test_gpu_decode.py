@@ -22,6 +22,23 @@ def lz():
     return lz
 
 
+def test_config1_fastq_bit_exact(orc, lz):
+    """12,000-record synthetic FASTQ, 16 KiB blocks: device bytes == oracle
+    bytes == source, per-block FNV checked on the device."""
+    from gen.fastq import fastq
+    x, _ = fastq(n_records=12000, seed=1)
+    a = orc.encode(x, kind=1, level_penalty=32)
+    rc, ref = orc.decode(a)
+    assert rc == 0 and ref == x
+    arc = lz.Archive(a)
+    for mode, wg in ((0, 2), (1, 1), (1, 2)):
+        assert _decode(arc, mode, wg) == ref
+    out = arc.decode_all()
+    tree = int(arc.verify(out).cpu().item()) & 0xFFFFFFFFFFFFFFFF
+    arc.sync_status()
+    assert tree == orc.info(a).source_fnv
+
+
 def _corpus():
     rng = np.random.default_rng(17)
     c = {}
@@ -64,23 +81,6 @@ def test_fastq_lanes(orc, lz, lanes):
     arc = lz.Archive(a)
     for mode in (0, 1):
         assert _decode(arc, mode) == x
-
-
-def test_config1_fastq_bit_exact(orc, lz):
-    """12,000-record synthetic FASTQ, 16 KiB blocks: device bytes == oracle
-    bytes == source, per-block FNV checked on the device."""
-    from gen.fastq import fastq
-    x, _ = fastq(n_records=12000, seed=1)
-    a = orc.encode(x, kind=1, level_penalty=32)
-    rc, ref = orc.decode(a)
-    assert rc == 0 and ref == x
-    arc = lz.Archive(a)
-    for mode, wg in ((0, 2), (1, 1), (1, 2)):
-        assert _decode(arc, mode, wg) == ref
-    out = arc.decode_all()
-    tree = int(arc.verify(out).cpu().item()) & 0xFFFFFFFFFFFFFFFF
-    arc.sync_status()
-    assert tree == orc.info(a).source_fnv
 
 
 def test_fasta_bit_exact(orc, lz):
