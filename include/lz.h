@@ -73,6 +73,9 @@ typedef struct lz_info {
   uint64_t archive_len;     /* total archive bytes                           */
   uint64_t source_fnv;      /* FNV-1a-64 over the LE64 block hashes          */
   uint64_t workspace_bytes; /* device workspace lz_open needs                */
+  uint64_t literal_bytes;   /* sum of literal-stream lengths (lz_get_info only);
+                               N - literal_bytes = bytes copied by matches    */
+  uint64_t payload_bytes;   /* compressed block payload bytes                 */
   uint32_t block_log2, max_level, n_levels, offset_width, max_record_len, kind;
 } lz_info;
 

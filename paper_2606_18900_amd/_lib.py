@@ -39,7 +39,8 @@ class Params(C.Structure):
 class Info(C.Structure):
     _fields_ = [("n", C.c_uint64), ("n_blocks", C.c_uint64), ("n_reads", C.c_uint64),
                 ("archive_len", C.c_uint64), ("source_fnv", C.c_uint64),
-                ("workspace_bytes", C.c_uint64), ("block_log2", C.c_uint32),
+                ("workspace_bytes", C.c_uint64), ("literal_bytes", C.c_uint64),
+                ("payload_bytes", C.c_uint64), ("block_log2", C.c_uint32),
                 ("max_level", C.c_uint32), ("n_levels", C.c_uint32),
                 ("offset_width", C.c_uint32), ("max_record_len", C.c_uint32),
                 ("kind", C.c_uint32)]

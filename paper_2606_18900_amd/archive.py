@@ -67,6 +67,10 @@ class Archive:
         self.h = C.c_void_p()
         check(lib().lz_open(_ptr(self.d_archive), self.d_archive.numel(), _ptr(self.ws),
                             self.ws.numel(), _stream(stream), C.byref(self.h)))
+        full = _lib.Info()
+        check(lib().lz_get_info(self.h, C.byref(full)))
+        self.literal_bytes = int(full.literal_bytes)
+        self.payload_bytes = int(full.payload_bytes)
 
     # -- properties
     @property

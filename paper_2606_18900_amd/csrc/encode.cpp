@@ -14,8 +14,9 @@
 //   among the earlier blocks the source touches; score = length - beta * lv;
 //   drop lv > D - 1 or score < m; best score wins, then lower lv, then the
 //   first candidate seen.  A match advances p by its length, otherwise p += 1.
-// The parse is sequential (levels feed back into later choices); the per-block
-// stream coding, hashing and table counting run on host threads.
+// Levels feed back into later choices, so the policy is sequential; parse_impl
+// computes exactly those choices with host threads (see there), and the
+// per-block stream coding runs on host threads too.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -24,6 +25,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <thread>
+#include <memory>
 #include <vector>
 
 #include "lz.h"
@@ -91,117 +93,182 @@ struct Parse {
 template <typename F>
 void parallel_for(uint64_t n, unsigned threads, F&& f);
 
+// The parse is defined sequentially (see the file comment); this computes the
+// same sequences with host threads:
+//  1. the hash of every insertable position;
+//  2. for every position its previous same-hash position and, per hash, the
+//     first position — built per hash partition, each partition scanned in
+//     increasing position order with a cache-sized local head table.  Walking
+//     these links from p visits exactly what the sequential chain holds at p;
+//  3. blocks are claimed in increasing order; a block's parse only needs the
+//     final level of an earlier block when a candidate from it could still be
+//     accepted (length - beta >= m), and then waits for that block to finish.
+//     Earlier blocks are claimed earlier, so every wait ends.
 template <typename Pos>
 int parse_impl(const uint8_t* x, uint64_t n, const lz_params& pr, unsigned threads, Parse& out) {
   const uint32_t bl = pr.block_log2;
   const uint64_t B = 1ull << bl, nb = (n + B - 1) >> bl;
-  const uint32_t h = pr.hash_len, m = pr.min_match, D = pr.max_level;
+  const uint32_t h = pr.hash_len, m = pr.min_match, D = pr.max_level, H = pr.hash_bits;
   const uint64_t C = pr.chain_depth ? pr.chain_depth : ~0ull;
   const uint64_t win = pr.window_log2 ? (1ull << pr.window_log2) : ~0ull;
   const int64_t beta = pr.level_penalty;
   const Pos kNone = (Pos)~(Pos)0;
-  const Hasher hash(h, pr.hash_bits);
-  // hash of every insertable position, computed in parallel chunks
+  const Hasher hash(h, H);
   const uint64_t nh = n >= h ? n - h + 1 : 0;
+  const uint64_t chunk = 1 << 20, nchunks = (nh + chunk - 1) / chunk;
   std::vector<uint32_t> hv(nh ? nh : 1);
-  const uint64_t chunk = 1 << 20;
-  parallel_for((nh + chunk - 1) / chunk, threads, [&](uint64_t c, unsigned) {
+  parallel_for(nchunks, threads, [&](uint64_t c, unsigned) {
     const uint64_t e = std::min(nh, (c + 1) * chunk);
     for (uint64_t p = c * chunk; p < e; p++) hv[p] = (uint32_t)hash(x, p, n);
   });
-  // head and anchor of a hash share one 2-entry slot (one cache line)
-  std::vector<Pos> ha(2ull << pr.hash_bits, kNone);
-  // prev link of position q lives at q & ring_mask (a full array without a window)
-  uint64_t ring = n;
-  if (pr.window_log2 && (1ull << pr.window_log2) < n) ring = 1ull << pr.window_log2;
-  const uint64_t ring_mask = (ring == n) ? ~0ull : ring - 1;
-  std::vector<Pos> prev(ring ? ring : 1, kNone);
-  constexpr uint64_t kAhead = 24;
-
-  out.seq_ptr.assign(nb + 1, 0);
-  out.level.assign(nb, 0);
-  out.dep_ptr.assign(nb + 1, 0);
-  std::vector<uint8_t> mark(nb, 0);
-  std::vector<uint32_t> touched;
-  uint64_t ins = 0;
-  for (uint64_t b = 0; b < nb; b++) {
-    const uint64_t sb = b << bl, eb = std::min(sb + B, n);
-    uint64_t p = sb, lit = sb;
-    uint32_t blevel = 0;
-    while (p < eb) {
-      for (; ins < p; ins++) {
-        if (ins >= nh) continue;
-        if (ins + kAhead < nh) __builtin_prefetch(&ha[2ull * hv[ins + kAhead]], 1, 1);
-        Pos* slot = &ha[2ull * hv[ins]];
-        prev[ins & ring_mask] = slot[0];
-        slot[0] = (Pos)ins;
-        if (slot[1] == kNone) slot[1] = (Pos)ins;
-      }
-      uint64_t bestL = 0, bestQ = 0;
-      uint32_t bestLv = 0;
-      int64_t bestSc = 0;
-      if (p + m <= eb) {
-        const Pos* slot = &ha[2ull * hv[p]];
-        const Pos a = slot[1];
-        bool anchor_seen = false;
-        auto consider = [&](uint64_t q) {
-          uint64_t L = lcp(x, q, p, eb - p);
-          if (L < m) return;
-          uint32_t lv = 0;
-          if (q < sb) {
-            uint64_t hi = std::min(q + L, sb);
-            uint32_t mx = 0;
-            for (uint64_t k = q >> bl; k <= (hi - 1) >> bl; k++) mx = std::max<uint32_t>(mx, out.level[k]);
-            lv = mx + 1;
-          }
-          if (lv > D - 1) return;
-          int64_t sc = (int64_t)L - beta * (int64_t)lv;
-          if (sc < (int64_t)m) return;
-          if (bestL == 0 || sc > bestSc || (sc == bestSc && lv < bestLv)) {
-            bestSc = sc;
-            bestL = L;
-            bestQ = q;
-            bestLv = lv;
-          }
-        };
-        Pos q = slot[0];
-        uint64_t cnt = 0;
-        while (q != kNone && cnt < C && p - (uint64_t)q <= win) {
-          if (q == a) anchor_seen = true;
-          consider(q);
-          q = prev[(uint64_t)q & ring_mask];
-          cnt++;
-        }
-        if (a != kNone && !anchor_seen) consider(a);
-      }
-      if (bestL) {
-        out.ll.push_back((uint32_t)(p - lit));
-        out.ml.push_back((uint32_t)bestL);
-        out.of.push_back(bestQ);
-        if (bestQ < sb) {
-          uint64_t hi = std::min(bestQ + bestL, sb);
-          for (uint64_t k = bestQ >> bl; k <= (hi - 1) >> bl; k++)
-            if (!mark[k]) { mark[k] = 1; touched.push_back((uint32_t)k); }
-        }
-        blevel = std::max(blevel, bestLv);
-        p += bestL;
-        lit = p;
-      } else {
-        p++;
-      }
-    }
-    if (lit < eb) {
-      out.ll.push_back((uint32_t)(eb - lit));
-      out.ml.push_back(0);
-      out.of.push_back(0);
-    }
-    out.seq_ptr[b + 1] = out.ll.size();
-    out.level[b] = (uint16_t)blevel;
-    std::sort(touched.begin(), touched.end());
-    for (uint32_t k : touched) { mark[k] = 0; out.dep_idx.push_back(k); }
-    touched.clear();
-    out.dep_ptr[b + 1] = out.dep_idx.size();
+  // 2. counting sort of positions by hash partition (top bits), then links
+  const uint32_t pbits = std::min<uint32_t>(8, H), np = 1u << pbits, shift = H - pbits;
+  std::vector<uint64_t> cnt(nchunks * np, 0), pstart(np + 1, 0);
+  parallel_for(nchunks, threads, [&](uint64_t c, unsigned) {
+    const uint64_t e = std::min(nh, (c + 1) * chunk);
+    uint64_t* hc = &cnt[c * np];
+    for (uint64_t p = c * chunk; p < e; p++) hc[hv[p] >> shift]++;
+  });
+  for (uint32_t k = 0; k < np; k++) {
+    uint64_t tot = 0;
+    for (uint64_t c = 0; c < nchunks; c++) { uint64_t v = cnt[c * np + k]; cnt[c * np + k] = tot; tot += v; }
+    pstart[k + 1] = pstart[k] + tot;
   }
+  std::vector<Pos> order(nh ? nh : 1);
+  parallel_for(nchunks, threads, [&](uint64_t c, unsigned) {
+    const uint64_t e = std::min(nh, (c + 1) * chunk);
+    std::vector<uint64_t> cur(np);
+    for (uint32_t k = 0; k < np; k++) cur[k] = pstart[k] + cnt[c * np + k];
+    for (uint64_t p = c * chunk; p < e; p++) order[cur[hv[p] >> shift]++] = (Pos)p;
+  });
+  std::vector<Pos> prev(nh ? nh : 1), first(1ull << H, kNone);
+  parallel_for(np, threads, [&](uint64_t k, unsigned) {
+    std::vector<Pos> head(1ull << shift, kNone);
+    const uint32_t lmask = (1u << shift) - 1;
+    for (uint64_t i = pstart[k]; i < pstart[k + 1]; i++) {
+      const Pos p = order[i];
+      const uint32_t hh = hv[p];
+      prev[p] = head[hh & lmask];
+      head[hh & lmask] = p;
+      if (first[hh] == kNone) first[hh] = p;
+    }
+  });
+  std::vector<Pos>().swap(order);
+
+  // 3. greedy parse of the blocks on worker threads
+  struct BlockOut {
+    std::vector<uint32_t> ll, ml, deps;
+    std::vector<uint64_t> of;
+  };
+  std::vector<BlockOut> bo(nb);
+  out.level.assign(nb, 0);
+  std::unique_ptr<std::atomic<uint8_t>[]> done(new std::atomic<uint8_t>[nb ? nb : 1]);
+  for (uint64_t b = 0; b < nb; b++) done[b].store(0, std::memory_order_relaxed);
+  std::atomic<uint64_t> next{0};
+  auto level_of = [&](uint64_t k) -> uint32_t {
+    while (!done[k].load(std::memory_order_acquire)) std::this_thread::yield();
+    return out.level[k];
+  };
+  auto work = [&]() {
+    for (;;) {
+      const uint64_t b = next.fetch_add(1);
+      if (b >= nb) break;
+      BlockOut& o = bo[b];
+      const uint64_t sb = b << bl, eb = std::min(sb + B, n);
+      uint64_t p = sb, lit = sb;
+      uint32_t blevel = 0;
+      while (p < eb) {
+        uint64_t bestL = 0, bestQ = 0;
+        uint32_t bestLv = 0;
+        int64_t bestSc = 0;
+        if (p + m <= eb) {
+          Pos a = first[hv[p]];
+          if ((uint64_t)a >= p) a = kNone;     // no earlier position with this hash
+          bool anchor_seen = false;
+          auto consider = [&](uint64_t q) {
+            const uint64_t L = lcp(x, q, p, eb - p);
+            if (L < m) return;
+            uint32_t lv = 0;
+            if (q < sb) {
+              // best case for a source in earlier blocks is level 1: if even
+              // that loses (or is rejected), the candidate cannot change the
+              // choice, so its level is not needed
+              const int64_t ub = (int64_t)L - beta;
+              if (ub < (int64_t)m) return;
+              if (bestL && (ub < bestSc || (ub == bestSc && bestLv <= 1))) return;
+              const uint64_t hi = std::min(q + L, sb);
+              uint32_t mx = 0;
+              for (uint64_t k = q >> bl; k <= (hi - 1) >> bl; k++) mx = std::max(mx, level_of(k));
+              lv = mx + 1;
+            }
+            if (lv > D - 1) return;
+            const int64_t sc = (int64_t)L - beta * (int64_t)lv;
+            if (sc < (int64_t)m) return;
+            if (bestL == 0 || sc > bestSc || (sc == bestSc && lv < bestLv)) {
+              bestSc = sc;
+              bestL = L;
+              bestQ = q;
+              bestLv = lv;
+            }
+          };
+          Pos q = prev[p];
+          uint64_t c = 0;
+          while (q != kNone && c < C && p - (uint64_t)q <= win) {
+            if (q == a) anchor_seen = true;
+            consider(q);
+            q = prev[q];
+            c++;
+          }
+          if (a != kNone && !anchor_seen) consider(a);
+        }
+        if (bestL) {
+          o.ll.push_back((uint32_t)(p - lit));
+          o.ml.push_back((uint32_t)bestL);
+          o.of.push_back(bestQ);
+          if (bestQ < sb) {
+            const uint64_t hi = std::min(bestQ + bestL, sb);
+            for (uint64_t k = bestQ >> bl; k <= (hi - 1) >> bl; k++) o.deps.push_back((uint32_t)k);
+          }
+          blevel = std::max(blevel, bestLv);
+          p += bestL;
+          lit = p;
+        } else {
+          p++;
+        }
+      }
+      if (lit < eb) {
+        o.ll.push_back((uint32_t)(eb - lit));
+        o.ml.push_back(0);
+        o.of.push_back(0);
+      }
+      std::sort(o.deps.begin(), o.deps.end());
+      o.deps.erase(std::unique(o.deps.begin(), o.deps.end()), o.deps.end());
+      out.level[b] = (uint16_t)blevel;
+      done[b].store(1, std::memory_order_release);
+    }
+  };
+  {
+    std::vector<std::thread> ts;
+    for (unsigned t = 1; t < threads; t++) ts.emplace_back(work);
+    work();
+    for (auto& t : ts) t.join();
+  }
+  out.seq_ptr.assign(nb + 1, 0);
+  out.dep_ptr.assign(nb + 1, 0);
+  for (uint64_t b = 0; b < nb; b++) {
+    out.seq_ptr[b + 1] = out.seq_ptr[b] + bo[b].ll.size();
+    out.dep_ptr[b + 1] = out.dep_ptr[b] + bo[b].deps.size();
+  }
+  out.ll.resize(out.seq_ptr[nb]);
+  out.ml.resize(out.seq_ptr[nb]);
+  out.of.resize(out.seq_ptr[nb]);
+  out.dep_idx.resize(out.dep_ptr[nb]);
+  parallel_for(nb, threads, [&](uint64_t b, unsigned) {
+    std::copy(bo[b].ll.begin(), bo[b].ll.end(), out.ll.begin() + out.seq_ptr[b]);
+    std::copy(bo[b].ml.begin(), bo[b].ml.end(), out.ml.begin() + out.seq_ptr[b]);
+    std::copy(bo[b].of.begin(), bo[b].of.end(), out.of.begin() + out.seq_ptr[b]);
+    std::copy(bo[b].deps.begin(), bo[b].deps.end(), out.dep_idx.begin() + out.dep_ptr[b]);
+  });
   return LZ_OK;
 }
 

@@ -81,5 +81,6 @@ struct lz_handle {
   lz_tuning tune;
   int n_cu;
   uint32_t level_count[kMaxLevels];   // host copy of the whole-file level histogram
-  uint32_t epoch;                     // host mirror of the completion epoch
+  uint64_t literal_bytes;             // sum of n_lit over blocks
+  uint64_t payload_bytes;             // end of the last block payload
 };

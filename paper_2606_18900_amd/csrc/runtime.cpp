@@ -195,12 +195,13 @@ extern "C" int lz_open(const uint8_t* d_archive, uint64_t len, void* d_ws, uint6
   const uint32_t D = hdr[9];
   std::vector<uint16_t> lv(nb);
   uint32_t count[kMaxLevels] = {0};
-  uint64_t prev_end = 0;
+  uint64_t prev_end = 0, lit_total = 0;
   const uint64_t paylen = pay_end - v.off_payload;
   for (uint64_t b = 0; b < nb; b++) {
     const uint8_t* e = meta.data() + v.off_dir + b * kDirEntry;
     const uint64_t po = rd64(e), pl = rd32(e + 8);
     lv[b] = (uint16_t)rd16(e + 20);
+    lit_total += rd32(e + 16);
     if (po < prev_end || !fits(po, pl, paylen) || (po & 15)) return lz_fail(LZ_EFORMAT, "block %llu payload out of bounds", (unsigned long long)b);
     prev_end = po + pl;
     if (lv[b] >= D || rd32(e + 12) < 1) return lz_fail(LZ_EFORMAT, "block %llu level or sequence count invalid", (unsigned long long)b);
@@ -256,6 +257,8 @@ extern "C" int lz_open(const uint8_t* d_archive, uint64_t len, void* d_ws, uint6
   h->ws.frontier = (uint32_t*)(w + L.frontier);
   h->ws.ctl = (uint32_t*)(w + L.ctl);
   std::memcpy(h->level_count, count, sizeof(count));
+  h->literal_bytes = lit_total;
+  h->payload_bytes = prev_end;
   h->tune.sync_mode = 1;
   h->tune.wg_per_cu = 2;
   h->tune.spin_limit = 0;
@@ -299,6 +302,8 @@ extern "C" int lz_get_info(const lz_handle* h, lz_info* out) {
   out->offset_width = h->av.offset_width;
   out->max_record_len = h->av.max_record_len;
   out->kind = h->av.kind;
+  out->literal_bytes = h->literal_bytes;
+  out->payload_bytes = h->payload_bytes;
   return LZ_OK;
 }
 
