@@ -198,8 +198,8 @@ def normalize(counts, prob_bits: int):
     return rc, f
 
 
-def rans_lanes(n: int, max_lanes: int) -> int:
-    return int(lib().orc_rans_lanes(C.c_uint32(n), C.c_uint32(max_lanes)))
+def rans_lanes(n: int, max_lanes: int, per_lane: int = 16) -> int:
+    return int(lib().orc_rans_lanes(C.c_uint32(n), C.c_uint32(max_lanes), C.c_uint32(per_lane)))
 
 
 def rans_encode(sym, freq, prob_bits: int, lanes: int):

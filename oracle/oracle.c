@@ -138,10 +138,11 @@ int orc_normalize(const uint64_t* counts, uint32_t P, uint16_t* freq) {
   return ORC_OK;
 }
 
-/* Lanes of a stream of n symbols: the largest power of two <= n/16, at least
- * 1, at most max_lanes. */
-int orc_rans_lanes(uint32_t n, uint32_t max_lanes) {
-  uint32_t q = n >> 4, k = 1;
+/* Lanes of a stream of n symbols: the largest power of two <= n/s, at least
+ * 1, at most max_lanes, with s = 16 symbols per lane for the literal stream
+ * and s = 4 for the (short) CMD, MLEN and OFF streams. */
+int orc_rans_lanes(uint32_t n, uint32_t max_lanes, uint32_t per_lane) {
+  uint32_t q = n / per_lane, k = 1;
   while (k * 2 <= q) k *= 2;
   return (int)(k < max_lanes ? k : max_lanes);
 }
@@ -512,7 +513,8 @@ static int offset_width(uint64_t n) {
  * EMPTY for n = 0, CONST for a single distinct symbol, else rANS unless its
  * body would be >= n bytes, in which case the bytes are stored RAW. */
 static int write_stream(buf_t* b, const uint8_t* sym, uint32_t n,
-                        const uint16_t* freq, uint32_t P, uint32_t max_lanes) {
+                        const uint16_t* freq, uint32_t P, uint32_t max_lanes,
+                        uint32_t per_lane) {
   uint8_t hdr[16];
   memset(hdr, 0, 16);
   put32(hdr + 4, n);
@@ -527,7 +529,7 @@ static int write_stream(buf_t* b, const uint8_t* sym, uint32_t n,
     hdr[1] = sym[0];
     return buf_put(b, hdr, 16);
   }
-  uint32_t K = (uint32_t)orc_rans_lanes(n, max_lanes);
+  uint32_t K = (uint32_t)orc_rans_lanes(n, max_lanes, per_lane);
   uint8_t* body = NULL;
   uint64_t blen = 0;
   uint32_t nw = 0;
@@ -652,7 +654,7 @@ int orc_encode(const uint8_t* x, uint64_t n, const orc_params* pr,
     for (int t = 0; t < 4 && !rc; t++) {
       int k = order[t];
       rc = write_stream(&pay, sbuf[k], slen[k], freq[k], pr->prob_bits[k],
-                        k == K_LIT ? pr->lit_lanes : pr->seq_lanes);
+                        k == K_LIT ? pr->lit_lanes : pr->seq_lanes, k == K_LIT ? 16 : 4);
     }
     uint64_t sb = b * B, eb = sb + B < n ? sb + B : n;
     bh[b] = orc_fnv1a64(x + sb, eb - sb, FNV_BASIS);
@@ -882,7 +884,7 @@ static int read_stream(const view_t* v, int kind, const uint8_t* blk,
     case MODE_RANS: {
       uint32_t maxK = kind == K_LIT ? v->lit_lanes : v->seq_lanes;
       if (K < 1 || K > maxK || n == 0 || !in_bounds(body, bl, blen)) return ORC_ECORRUPT;
-      if (K != (uint32_t)orc_rans_lanes(n, maxK)) return ORC_ECORRUPT;
+      if (K != (uint32_t)orc_rans_lanes(n, maxK, kind == K_LIT ? 16 : 4)) return ORC_ECORRUPT;
       rc = orc_rans_decode(blk + body, bl, n, nw, v->freq[kind], v->P[kind], K, out);
       break;
     }

@@ -57,7 +57,7 @@ uint64_t orc_fnv_basis(void);
 
 /* Entropy stage pieces, exposed for the unit pins. */
 int orc_normalize(const uint64_t* counts, uint32_t prob_bits, uint16_t* freq);
-int orc_rans_lanes(uint32_t n, uint32_t max_lanes);
+int orc_rans_lanes(uint32_t n, uint32_t max_lanes, uint32_t per_lane);
 int orc_rans_encode(const uint8_t* sym, uint32_t n, const uint16_t* freq,
                     uint32_t prob_bits, uint32_t lanes, uint8_t** body,
                     uint64_t* body_len, uint32_t* n_words);

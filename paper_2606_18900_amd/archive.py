@@ -120,12 +120,26 @@ class Archive:
         check(lib().lz_decode_all(self.h, _ptr(out), out.numel(), _stream(stream)))
         return out[: self.n]
 
+    def scratch_bytes(self, n_requests: int, n_slots: int | None = None) -> int:
+        """Scratch for a request call: per-request spans and prefix sums, then
+        n_slots block-sized slots (default: one per block, a bound on any
+        closure)."""
+        n = max(1, n_requests)
+        head = (16 * n + 16 * (n + 1) + 255) & ~255
+        slots = self.n_blocks if n_slots is None else n_slots
+        return head + slots * (1 << int(self.info.block_log2))
+
+    def _scratch(self, n_requests: int, scratch, n_slots=None) -> torch.Tensor:
+        if scratch is None:
+            scratch = torch.empty(self.scratch_bytes(n_requests, n_slots), dtype=torch.uint8,
+                                  device=self.device)
+        return scratch
+
     def decode_range(self, offset: int, length: int, out: torch.Tensor | None = None,
                      scratch: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         if out is None:
             out = torch.empty(max(length, 1), dtype=torch.uint8, device=self.device)
-        if scratch is None:
-            scratch = self.default_scratch(1, length)
+        scratch = self._scratch(1, scratch)
         check(lib().lz_decode_range(self.h, offset, length, _ptr(out), _ptr(scratch),
                                     scratch.numel(), _stream(stream)))
         return out[:length]
@@ -140,15 +154,15 @@ class Archive:
             out = torch.empty(cap, dtype=torch.uint8, device=self.device)
         if offsets is None:
             offsets = torch.empty(n + 1, dtype=torch.int64, device=self.device)
-        if scratch is None:
-            scratch = self.default_scratch(n, cap)
+        scratch = self._scratch(n, scratch)
         check(lib().lz_read_lookup(self.h, _ptr(ids), n, _ptr(out), out.numel(), _ptr(offsets),
                                    _ptr(scratch), scratch.numel(), _stream(stream)))
         return out, offsets
 
     def decode_batch(self, reqs: torch.Tensor, n: torch.Tensor, n_max: int, out: torch.Tensor,
                      offsets: torch.Tensor, scratch: torch.Tensor, stream=None):
-        """reqs: device int64 [n_max, 3] (kind, a, b); n: device uint32/int32 [1]."""
+        """reqs: device int64 [n_max, 3] rows (kind, a, b); n: device int32 [1]
+        holding the live request count (<= n_max)."""
         check(lib().lz_decode_batch(self.h, _ptr(reqs), _ptr(n), n_max, _ptr(out), out.numel(),
                                     _ptr(offsets), _ptr(scratch), scratch.numel(), _stream(stream)))
 
@@ -161,10 +175,3 @@ class Archive:
 
     def sync_status(self, stream=None) -> None:
         check(lib().lz_sync_status(self.h, _stream(stream)))
-
-    def default_scratch(self, n_requests: int, out_bytes: int) -> torch.Tensor:
-        """Scratch sized for request spans plus one slot per block of the file
-        (an upper bound on any closure)."""
-        B = 1 << int(self.info.block_log2)
-        nbytes = 64 * (n_requests + 1) + B * self.n_blocks + 4096
-        return torch.empty(nbytes, dtype=torch.uint8, device=self.device)

@@ -307,8 +307,10 @@ int normalize(const uint64_t* counts, uint32_t P, uint16_t* freq) {
   return LZ_OK;
 }
 
-uint32_t lanes_for(uint32_t n, uint32_t max_lanes) {
-  uint32_t q = n >> 4, k = 1;
+// largest power of two <= n / per_lane, at least 1, at most max_lanes
+// (16 symbols per lane for literals, 4 for the short CMD/MLEN/OFF streams)
+uint32_t lanes_for(uint32_t n, uint32_t max_lanes, uint32_t per_lane) {
+  uint32_t q = n / per_lane, k = 1;
   while (k * 2 <= q) k *= 2;
   return std::min(k, max_lanes);
 }
@@ -360,7 +362,7 @@ void rans_body(const uint8_t* sym, uint32_t n, const Table& t, uint32_t K,
 }
 
 void put_stream(std::vector<uint8_t>& outb, const uint8_t* sym, uint32_t n, const Table& t,
-                uint32_t max_lanes) {
+                uint32_t max_lanes, uint32_t per_lane) {
   uint8_t hdr[16] = {0};
   std::memcpy(hdr + 4, &n, 4);
   auto pad = [&]() { while (outb.size() & 15) outb.push_back(0); };
@@ -377,7 +379,7 @@ void put_stream(std::vector<uint8_t>& outb, const uint8_t* sym, uint32_t n, cons
     outb.insert(outb.end(), hdr, hdr + 16);
     return;
   }
-  uint32_t K = lanes_for(n, max_lanes), nw = 0;
+  uint32_t K = lanes_for(n, max_lanes, per_lane), nw = 0;
   std::vector<uint8_t> body;
   rans_body(sym, n, t, K, body, nw);
   if (body.size() >= n) {
@@ -543,7 +545,8 @@ extern "C" int lz_encode(const uint8_t* x, uint64_t n, const lz_params* pp, uint
     build(b, s);
     static const int order[4] = {kCmd, kMlen, kOff, kLit};
     for (int k : order)
-      put_stream(pay[b], s[k].data(), (uint32_t)s[k].size(), tab[k], k == kLit ? pr.lit_lanes : pr.seq_lanes);
+      put_stream(pay[b], s[k].data(), (uint32_t)s[k].size(), tab[k], k == kLit ? pr.lit_lanes : pr.seq_lanes,
+                 k == kLit ? 16u : 4u);
     const uint64_t sb = b << bl, eb = std::min(sb + B, n);
     bh[b] = fnv1a(x + sb, eb - sb, kFnvBasis);
     nlit[b] = (uint32_t)s[kLit].size();

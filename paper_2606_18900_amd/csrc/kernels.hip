@@ -1,16 +1,16 @@
 // Device decoder for container format v1 on gfx950 (CDNA4, wave64).
 //
 // One workgroup of 256 threads (4 waves) decodes one block at a time:
-//   1. stage the rANS bodies of the command (CMD), match-length (MLEN) and
-//      offset (OFF) streams in LDS; waves 0..2 decode one stream each;
+//   1. waves 0..2 decode the command (CMD), match-length (MLEN) and offset
+//      (OFF) streams, one each, reading rANS words straight from HBM;
 //   2. block-wide exclusive scans turn literal-run and match lengths into
 //      literal and output positions (command placement);
 //   3. the literal stream's 64-lane groups are decoded by one wave each and
 //      every literal is written straight to its output position in an LDS tile;
 //   4. matches whose source lies wholly in earlier blocks are copied in
-//      parallel; then the remaining matches are copied in order, a chunk of
-//      min(period, 64) bytes at a time, which reproduces the byte-sequential
-//      overlap rule out[p+k] = out[OF+k];
+//      parallel; then the remaining matches are copied in order, each with
+//      out[p+k] = out[OF + (k mod (p-OF))], the byte-sequential overlap rule
+//      out[p+k] = out[OF+k] unrolled, so all bytes of a match go at once;
 //   5. the tile is written to HBM with 16-byte stores and, in the persistent
 //      kernel, the block's completion flag is released.
 // Blocks are taken in dependency-level order ("wavefront" order, paper:
@@ -30,15 +30,13 @@ constexpr int kWaves = kWG / 64;
 constexpr uint32_t kB = 1u << kMaxBlockLog2;      // largest block: 16 KiB tile
 constexpr uint32_t kMaxSeq = 1025;                // B/m + 1 for B = 16 KiB, m = 16
 constexpr uint32_t kLutLit = 1u << kMaxPLit;      // 4096 packed literal entries
-constexpr uint32_t kStage = kB;                   // staging bytes for rANS bodies
 constexpr uint32_t kL = 1u << 16;                 // rANS state lower bound
 
-// All LDS is static (about 61 KB): literal LUT, output tile, body staging,
-// small-stream cumulative tables, per-sequence tables.
+// All LDS is static (about 45 KB, three workgroups per CU): literal LUT,
+// output tile, small-stream cumulative tables, per-sequence tables.
 struct Smem {
   uint32_t lut[kLutLit];
-  uint8_t tile[kB];
-  alignas(16) uint8_t stage[kStage];
+  alignas(16) uint8_t tile[kB];
   uint16_t cum[3][257];        // CMD, MLEN, OFF cumulative frequencies
   uint16_t lit[kMaxSeq + 1];   // LL values, then exclusive scan of LL ([ns] = n_lit)
   uint16_t out[kMaxSeq + 1];   // ML values, then exclusive scan of LL+ML ([ns] = block length)
@@ -108,7 +106,7 @@ __device__ __forceinline__ bool parse_stream(const uint8_t* pay, uint32_t plen, 
     case kModeRans: {
       const uint32_t G = (s.K + 63) >> 6;
       if (s.K < 1 || s.K > maxK || !s.n || s.body + s.blen > plen) return false;
-      if ((uint64_t)s.blen != 4ull * s.K + 4ull * G + 2ull * s.nw || s.blen > kStage) return false;
+      if ((uint64_t)s.blen != 4ull * s.K + 4ull * G + 2ull * s.nw) return false;
       uint64_t sum = 0;
       for (uint32_t g = 0; g < G; g++) sum += ld32(pay + s.body + 4 * s.K + 4 * g);
       if (sum != s.nw) return false;
@@ -120,18 +118,15 @@ __device__ __forceinline__ bool parse_stream(const uint8_t* pay, uint32_t plen, 
   return true;
 }
 
-// Copy a rANS body to LDS staging at byte offset `at` (16-byte granules).
-__device__ __forceinline__ void stage_body(Smem& S, const uint8_t* pay, const Stream& s, uint32_t at) {
-  if (s.mode != kModeRans) return;
-  const uint4* src = reinterpret_cast<const uint4*>(pay + s.body);
-  uint4* dst = reinterpret_cast<uint4*>(S.stage + at);
-  const uint32_t n16 = (s.blen + 15u) >> 4;
-  for (uint32_t c = threadIdx.x; c < n16; c += kWG) dst[c] = src[c];
-}
-
 // Decode the symbols of 64-lane group g of a rANS stream with one wave.
-// `sym(x)` maps the state's slot to (symbol, f, slot - c) and `out(i, s)`
-// consumes symbol i.  True if every state ends at 2^16 and every word was read.
+// `body` is the record body in global memory (states, per-group word counts,
+// words).  `sym(u)` maps slot u to symbol | f << 8 | (u - c_s) << 20 and
+// `out(i, s)` consumes symbol i.  The group's 16-bit words are read through a
+// window of three 64-word slices held one word per lane; a lane needing word
+// idx (always inside the first two slices) takes it with a cross-lane shuffle,
+// and when 64 words have been consumed the window slides and the slice two
+// ahead is loaded, so loads run about five rounds ahead of use.
+// True if every state ends at 2^16 and every word of the group was read.
 template <class Sym, class Out>
 __device__ bool rans_group(const uint8_t* body, const Stream& s, uint32_t g, uint32_t P,
                            Sym&& sym, Out&& out) {
@@ -139,34 +134,46 @@ __device__ bool rans_group(const uint8_t* body, const Stream& s, uint32_t g, uin
   const uint32_t K = s.K, n = s.n, G = (K + 63) >> 6;
   const uint32_t k = (g << 6) + lane;
   const bool lane_ok = k < K;
-  const uint32_t* st = reinterpret_cast<const uint32_t*>(body);
-  const uint32_t* gw = st + K;
-  uint32_t woff = 0;
-  for (uint32_t q = 0; q < g; q++) woff += gw[q];
-  const uint32_t nwg = gw[g];
-  const uint16_t* W = reinterpret_cast<const uint16_t*>(gw + G) + woff;
-  uint32_t x = lane_ok ? st[k] : kL;
+  uint32_t woff = 0, nwg = 0;
+  for (uint32_t q = 0; q < G; q++) {
+    const uint32_t c = ld32(body + 4 * K + 4 * q);
+    if (q < g) woff += c;
+    if (q == g) nwg = c;
+  }
+  const uint16_t* W = reinterpret_cast<const uint16_t*>(body + 4 * K + 4 * G) + woff;
+  auto ldw = [&](uint32_t idx) -> uint32_t { return idx < nwg ? (uint32_t)W[idx] : 0u; };
+  uint32_t x = lane_ok ? ld32(body + 4 * k) : kL;
   bool ok = x >= kL && woff + nwg <= s.nw;
-  uint32_t pos = 0;
+  uint32_t w0 = ldw(lane), w1 = ldw(64 + lane), w2 = ldw(128 + lane);
+  uint32_t pos = 0, base = 0;
   const uint32_t rounds = (n + K - 1) / K;
   const uint32_t mask = (1u << P) - 1;
   uint32_t i = k;
   for (uint32_t r = 0; r < rounds; r++, i += K) {
     const bool act = lane_ok && i < n;
     if (act) {
-      const uint32_t e = sym(x & mask);          // symbol | f << 8 | bias << 20
+      const uint32_t e = sym(x & mask);
       x = __umul24((e >> 8) & 0xFFFu, x >> P) + (e >> 20);
       out(i, e & 0xFFu);
     }
     const bool need = act && x < kL;
     const uint64_t bal = __ballot(need);
-    if (need) {
-      const uint32_t idx = pos + mbcnt(bal);
-      const bool in = idx < nwg;
-      ok = ok && in;
-      x = (x << 16) | (in ? (uint32_t)W[idx] : 0u);
+    if (bal) {
+      const uint32_t local = (pos - base) + mbcnt(bal);      // < 128
+      const uint32_t a0 = __shfl(w0, (int)(local & 63), 64);
+      const uint32_t a1 = __shfl(w1, (int)(local & 63), 64);
+      if (need) {
+        ok = ok && pos + mbcnt(bal) < nwg;
+        x = (x << 16) | (local < 64 ? a0 : a1);
+      }
+      pos += (uint32_t)__popcll(bal);
+      if (pos - base >= 64) {
+        w0 = w1;
+        w1 = w2;
+        base += 64;
+        w2 = ldw(base + 128 + lane);
+      }
     }
-    pos += (uint32_t)__popcll(bal);
   }
   ok = ok && (!lane_ok || x == kL) && pos == nwg;
   return __ballot(!ok) == 0;
@@ -237,25 +244,13 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
     if (t == 0) latch(A.ctl, kStCorrupt);
     return;
   }
-  const uint32_t a_cmd = 0;
-  const uint32_t a_mln = a_cmd + (sc.mode == kModeRans ? ((sc.blen + 15u) & ~15u) : 0u);
-  const uint32_t a_off = a_mln + (sm.mode == kModeRans ? ((sm.blen + 15u) & ~15u) : 0u);
-  const uint32_t small_end = a_off + (so.mode == kModeRans ? ((so.blen + 15u) & ~15u) : 0u);
-  if (small_end > kStage) {
-    if (t == 0) latch(A.ctl, kStCorrupt);
-    return;
-  }
 
   // ---- stage 1: CMD -> lit[] (LL), MLEN -> out[] (ML), OFF -> oflo/ofhi
-  stage_body(S, pay, sc, a_cmd);
-  stage_body(S, pay, sm, a_mln);
-  stage_body(S, pay, so, a_off);
   for (uint32_t j = t; j < ns; j += kWG) { S.oflo[j] = 0; S.ofhi[j] = 0; }
   if (t == 0) { S.err = 0; S.nint = 0; }
   __syncthreads();
   if (wv < 3) {
     const Stream& s = wv == 0 ? sc : (wv == 1 ? sm : so);
-    const uint32_t at = wv == 0 ? a_cmd : (wv == 1 ? a_mln : a_off);
     const uint16_t* cum = S.cum[wv];
     uint8_t* dst8 = wv == 0 ? reinterpret_cast<uint8_t*>(S.lit) : reinterpret_cast<uint8_t*>(S.out);
     auto put = [&](uint32_t i, uint32_t v) {
@@ -271,7 +266,7 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
     };
     bool okw = true;
     if (s.mode == kModeRans) {
-      okw = rans_group(S.stage + at, s, 0, A.P[1 + wv],
+      okw = rans_group(pay + s.body, s, 0, A.P[1 + wv],
                        [&](uint32_t u) { return search_sym(cum, u); }, put);
     } else if (s.mode == kModeRaw) {
       const uint8_t* src = pay + s.body;
@@ -321,8 +316,6 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
   }
 
   // ---- stage 3: literals straight to their tile positions; external matches
-  stage_body(S, pay, sl, 0);
-  __syncthreads();
   {
     bool bad = false;
     uint32_t j = 0;                            // per-lane sequence cursor
@@ -339,7 +332,7 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
     if (sl.mode == kModeRans) {
       const uint32_t G = (sl.K + 63) >> 6;
       for (uint32_t g = wv; g < G; g += kWaves)
-        if (!rans_group(S.stage, sl, g, A.P[kLit], [&](uint32_t u) { return S.lut[u]; }, place)) bad = true;
+        if (!rans_group(pay + sl.body, sl, g, A.P[kLit], [&](uint32_t u) { return S.lut[u]; }, place)) bad = true;
     } else if (sl.mode == kModeRaw) {
       const uint8_t* src = pay + sl.body;
       for (uint32_t i = t; i < sl.n; i += kWG) place(i, src[i]);
@@ -368,8 +361,10 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
     return;
   }
 
-  // ---- stage 4: matches touching the block itself, in sequence order (wave 0),
-  // min(period, 64) bytes per step: out[p+k] = out[OF+k] byte-sequentially
+  // ---- stage 4: matches touching the block itself, in sequence order (wave 0).
+  // With period d = p - OF, out[p+k] = out[OF + (k mod d)] for every k (the
+  // byte-sequential overlap rule unrolled), and OF..OF+d-1 are final before the
+  // match starts, so all bytes of one match are copied at once, 64 per step.
   if (wv == 0) {
     const uint32_t cnt = min(S.nint, ns);
     if (lane == 0)
@@ -389,17 +384,21 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
       const uint32_t d0 = S.out[q] + L;
       const uint64_t of = (uint64_t)S.oflo[q] | ((uint64_t)S.ofhi[q] << 32);
       const uint64_t dabs = sb + d0;
-      const uint32_t step = dabs > of ? (dabs - of < 64 ? (uint32_t)(dabs - of) : 64u) : 1u;
-      for (uint32_t c = 0; c < M; c += step) {
+      const uint32_t d = dabs > of ? (dabs - of < kB ? (uint32_t)(dabs - of) : kB) : 1u;
+      uint32_t r = lane % d;               // (c + lane) mod d, kept incrementally
+      const uint32_t r64 = 64u % d;
+      for (uint32_t c = 0; c < M; c += 64) {
         const uint32_t k = c + lane;
-        if (lane < step && k < M && d0 + k < blen) {
-          const uint64_t s = of + k;
+        if (k < M && d0 + k < blen) {
+          const uint64_t s = of + r;
           const uint32_t v = s >= sb ? (uint32_t)S.tile[(uint32_t)(s - sb) & (kB - 1)] : src_byte(A, s, bad);
           S.tile[d0 + k] = (uint8_t)v;
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+        r += r64;
+        if (r >= d) r -= d;
       }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
     }
     if (bad && lane == 0) S.err = 1;
   }
@@ -654,7 +653,362 @@ int lz_launch_verify(lz_handle* h, const uint8_t* d_out, uint64_t* d_tree, void*
   return launch_ok("lz_verify");
 }
 
-int lz_launch_requests(lz_handle*, const lz_request*, const uint32_t*, uint64_t, uint64_t, uint64_t,
-                       const int64_t*, uint8_t*, uint64_t, uint64_t*, void*, uint64_t, hipStream_t) {
-  return lz_fail(LZ_EINVAL, "request decoding is not built yet");
+// ---- requests: ranges, read lookups, batches --------------------------------
+//
+// A batch is resolved by a fixed sequence of launches whose sizes are read on
+// the device, so the sequence can be captured once and replayed:
+//   begin   new request and completion epochs, counters cleared
+//   spans   request -> [start, end) bytes (read id through the read index)
+//   scan    exclusive prefix of lengths (output offsets) and of covering-block
+//           counts (request, block) pairs; capacity check
+//   mark    every covering block marked with the epoch and pushed on a list
+//   closure worklist over the dependency lists: each pushed block pushes its
+//           unmarked dependencies (transitive closure)
+//   levels  counting sort of the closure by dependency level; each block gets
+//           an address: straight into the output when it lies wholly inside an
+//           aligned single range, else a scratch slot
+//   decode  k_decode over the level-ordered closure (same body as whole-file)
+//   gather  requested bytes of scratch-resident blocks copied to the output
+namespace {
+
+struct ReqArgs {
+  const uint8_t* arc;
+  uint64_t n, off_dir, off_dep_ptr, off_dep_idx, off_ridx, n_reads;
+  uint32_t bl, mode, direct;
+  uint64_t a0, b0;            // mode 0: the single range
+  const int64_t* ids;         // mode 1: read ids
+  const lz_request* reqs;     // mode 2: requests
+  const uint32_t* d_n;        // mode 2: device request count
+  uint64_t n_max;
+  uint8_t* out;
+  uint64_t cap;
+  uint64_t* offsets;          // caller's offsets (n + 1) or null
+  uint64_t* spans;            // scratch: 2 per request
+  uint64_t* cnt_ptr;          // scratch: n + 1
+  uint64_t* offs;             // scratch: n + 1
+  uint8_t* slots;
+  uint64_t max_slots;
+  uint32_t* mark;
+  uint64_t* addr;
+  uint32_t* rqueue;
+  uint32_t* rlevel_ptr;
+  uint64_t* list;
+  uint32_t* ctl;
+};
+
+__device__ __forceinline__ uint64_t* ctl64(uint32_t* ctl, uint32_t w) { return reinterpret_cast<uint64_t*>(ctl + w); }
+
+__device__ __forceinline__ uint32_t aload(const uint32_t* p) {
+  return __hip_atomic_load(const_cast<uint32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// largest j in [0, n) with v[j] <= g (v nondecreasing, v[0] = 0)
+__device__ __forceinline__ uint32_t find_req(const uint64_t* v, uint32_t n, uint64_t g) {
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (v[mid] <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Mark block b with the request epoch; push it on the closure list if this
+// call marked it first.
+__device__ __forceinline__ void mark_push(const ReqArgs& R, uint32_t b, uint32_t epoch) {
+  const uint32_t old = __hip_atomic_fetch_max(R.mark + b, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (old >= epoch) return;
+  const uint32_t i = __hip_atomic_fetch_add(R.ctl + kCtlListTail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(R.list + i, ((uint64_t)epoch << 32) | b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void k_req_begin(ReqArgs R) {
+  const uint32_t t = threadIdx.x;
+  if (t < 64) R.ctl[kCtlLevelCnt + t] = 0;
+  if (t == 0) {
+    R.ctl[kCtlREpoch] += 1;
+    R.ctl[kCtlEpoch] += 1;
+    R.ctl[kCtlTicket] = 0;
+    R.ctl[kCtlListTail] = 0;
+    R.ctl[kCtlListHead] = 0;
+    R.ctl[kCtlListDone] = 0;
+    R.ctl[kCtlSlots] = 0;
+    uint64_t n = R.n_max;
+    if (R.mode == 2) n = min((uint64_t)*R.d_n, R.n_max);
+    R.ctl[kCtlNReq] = (uint32_t)n;
+    *ctl64(R.ctl, kCtlTotal) = 0;
+    *ctl64(R.ctl, kCtlPairs) = 0;
+  }
+}
+
+__device__ __forceinline__ bool read_span(const ReqArgs& R, int64_t r, uint64_t& s, uint64_t& e) {
+  if (!R.off_ridx || r < 0 || (uint64_t)r >= R.n_reads) return false;
+  s = ld64(R.arc + R.off_ridx + 8ull * (uint64_t)r);
+  e = ld64(R.arc + R.off_ridx + 8ull * (uint64_t)r + 8);
+  return true;
+}
+
+__global__ void k_req_spans(ReqArgs R) {
+  const uint32_t nreq = R.ctl[kCtlNReq];
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < nreq; j += gridDim.x * blockDim.x) {
+    uint64_t s = 0, e = 0;
+    bool ok = true;
+    if (R.mode == 0) {
+      s = R.a0;
+      e = R.a0 + R.b0;
+    } else if (R.mode == 1) {
+      ok = read_span(R, R.ids[j], s, e);
+    } else {
+      const lz_request q = R.reqs[j];
+      if (q.kind == 0) {
+        ok = read_span(R, q.a, s, e);
+      } else if (q.kind == 1 && q.a >= 0 && q.b >= 0 && (uint64_t)q.a <= R.n && (uint64_t)q.b <= R.n - (uint64_t)q.a) {
+        s = (uint64_t)q.a;
+        e = s + (uint64_t)q.b;
+      } else {
+        ok = false;
+      }
+    }
+    if (!ok) {
+      latch(R.ctl, kStRange);
+      s = e = 0;
+    }
+    R.spans[2 * j] = s;
+    R.spans[2 * j + 1] = e;
+  }
+}
+
+// One workgroup of 1024 threads: exclusive prefix sums of output lengths and
+// covering-block counts, in chunks of 1024 requests.
+__global__ void __launch_bounds__(1024) k_req_scan(ReqArgs R) {
+  __shared__ uint64_t wsum[2][16];
+  const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const uint32_t nreq = R.ctl[kCtlNReq];
+  uint64_t carry_len = 0, carry_cnt = 0;
+  for (uint32_t c0 = 0; c0 < nreq; c0 += 1024) {
+    const uint32_t j = c0 + t;
+    uint64_t len = 0, cnt = 0;
+    if (j < nreq) {
+      const uint64_t s = R.spans[2 * j], e = R.spans[2 * j + 1];
+      len = e - s;
+      cnt = e > s ? ((e - 1) >> R.bl) - (s >> R.bl) + 1 : 0;
+    }
+    uint64_t il = len, ic = cnt;
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint64_t yl = __shfl_up(il, d, 64), yc = __shfl_up(ic, d, 64);
+      if (lane >= (uint32_t)d) { il += yl; ic += yc; }
+    }
+    if (lane == 63) { wsum[0][wv] = il; wsum[1][wv] = ic; }
+    __syncthreads();
+    uint64_t bl = 0, bc = 0, tl = 0, tc = 0;
+    for (uint32_t q = 0; q < 16; q++) {
+      if (q < wv) { bl += wsum[0][q]; bc += wsum[1][q]; }
+      tl += wsum[0][q];
+      tc += wsum[1][q];
+    }
+    if (j < nreq) {
+      R.offs[j] = carry_len + bl + il - len;
+      R.cnt_ptr[j] = carry_cnt + bc + ic - cnt;
+      if (R.offsets) R.offsets[j] = carry_len + bl + il - len;
+    }
+    carry_len += tl;
+    carry_cnt += tc;
+    __syncthreads();
+  }
+  if (t == 0) {
+    R.offs[nreq] = carry_len;
+    R.cnt_ptr[nreq] = carry_cnt;
+    if (R.offsets) R.offsets[nreq] = carry_len;
+    *ctl64(R.ctl, kCtlTotal) = carry_len;
+    if (carry_len > R.cap) {
+      latch(R.ctl, kStCapacity);
+      carry_cnt = 0;           // nothing is decoded or gathered
+    }
+    *ctl64(R.ctl, kCtlPairs) = carry_cnt;
+  }
+}
+
+__global__ void k_req_mark(ReqArgs R) {
+  const uint64_t pairs = *ctl64(R.ctl, kCtlPairs);
+  const uint32_t nreq = R.ctl[kCtlNReq];
+  const uint32_t epoch = R.ctl[kCtlREpoch];
+  for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < pairs; g += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t j = find_req(R.cnt_ptr, nreq, g);
+    const uint64_t b = (R.spans[2 * j] >> R.bl) + (g - R.cnt_ptr[j]);
+    mark_push(R, (uint32_t)b, epoch);
+  }
+}
+
+// Transitive closure over the dependency lists with a shared worklist.  Each
+// thread takes list entries in turn; it stops when every pushed entry has
+// been expanded (done == tail read in that order: no entry can appear later).
+__global__ void k_closure(ReqArgs R, uint32_t spin_limit) {
+  const uint32_t epoch = aload(R.ctl + kCtlREpoch);
+  for (;;) {
+    const uint32_t i = __hip_atomic_fetch_add(R.ctl + kCtlListHead, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t spins = 0;
+    for (;;) {
+      if (i < aload(R.ctl + kCtlListTail)) break;
+      const uint32_t done = aload(R.ctl + kCtlListDone);
+      if (done == aload(R.ctl + kCtlListTail) && i >= done) return;
+      if (++spins > spin_limit) { latch(R.ctl, kStWatchdog); return; }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    uint64_t v;
+    spins = 0;
+    while (((v = __hip_atomic_load(R.list + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 32) != epoch) {
+      if (++spins > spin_limit) { latch(R.ctl, kStWatchdog); return; }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    const uint32_t b = (uint32_t)v;
+    const uint64_t d0 = ld64(R.arc + R.off_dep_ptr + 8ull * b), d1 = ld64(R.arc + R.off_dep_ptr + 8ull * (b + 1));
+    for (uint64_t k = d0; k < d1; k++) mark_push(R, ld32(R.arc + R.off_dep_idx + 4 * k), epoch);
+    __hip_atomic_fetch_add(R.ctl + kCtlListDone, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__device__ __forceinline__ uint32_t block_level(const ReqArgs& R, uint32_t b) {
+  const uint8_t* e = R.arc + R.off_dir + (uint64_t)b * kDirEntry + 20;
+  return min((uint32_t)e[0] | ((uint32_t)e[1] << 8), 63u);
+}
+
+__global__ void k_req_levels(ReqArgs R) {
+  const uint32_t cnt = R.ctl[kCtlListTail];
+  const uint64_t B = 1ull << R.bl;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
+    const uint32_t b = (uint32_t)R.list[i];
+    atomicAdd(R.ctl + kCtlLevelCnt + block_level(R, b), 1u);
+    const uint64_t sb = (uint64_t)b << R.bl, eb = min(sb + B, R.n);
+    uint64_t a = 0;
+    if (R.direct && sb >= R.a0 && eb <= R.a0 + R.b0 && ((sb - R.a0) & 15) == 0) {
+      a = reinterpret_cast<uint64_t>(R.out + (sb - R.a0));
+    } else {
+      const uint32_t slot = atomicAdd(R.ctl + kCtlSlots, 1u);
+      if (slot < R.max_slots) a = reinterpret_cast<uint64_t>(R.slots + (uint64_t)slot * B);
+      else latch(R.ctl, kStCapacity);
+    }
+    R.addr[b] = a;
+  }
+}
+
+__global__ void k_req_level_scan(ReqArgs R) {
+  if (threadIdx.x == 0) {
+    uint32_t s = 0;
+    for (uint32_t L = 0; L < 64; L++) {
+      R.rlevel_ptr[L] = s;
+      R.rlevel_ptr[65 + L] = s;
+      s += R.ctl[kCtlLevelCnt + L];
+    }
+    R.rlevel_ptr[64] = s;
+  }
+}
+
+__global__ void k_req_scatter(ReqArgs R) {
+  const uint32_t cnt = R.ctl[kCtlListTail];
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
+    const uint32_t b = (uint32_t)R.list[i];
+    const uint32_t pos = atomicAdd(R.rlevel_ptr + 65 + block_level(R, b), 1u);
+    R.rqueue[pos] = b;
+  }
+}
+
+// One workgroup per (request, covering block) pair: copy the requested part
+// of a block that was decoded into a scratch slot.
+__global__ void k_req_gather(ReqArgs R) {
+  const uint64_t pairs = *ctl64(R.ctl, kCtlPairs);
+  const uint32_t nreq = R.ctl[kCtlNReq];
+  const uint64_t B = 1ull << R.bl;
+  for (uint64_t g = blockIdx.x; g < pairs; g += gridDim.x) {
+    const uint32_t j = find_req(R.cnt_ptr, nreq, g);
+    const uint64_t s = R.spans[2 * j], e = R.spans[2 * j + 1];
+    const uint64_t b = (s >> R.bl) + (g - R.cnt_ptr[j]);
+    const uint64_t a = R.addr[b];
+    if (!a) continue;
+    const uint64_t sb = b << R.bl, eb = min(sb + B, R.n);
+    const uint64_t lo = max(sb, s), hi = min(eb, e);
+    if (hi <= lo) continue;
+    uint8_t* dst = R.out + R.offs[j] + (lo - s);
+    const uint8_t* src = reinterpret_cast<const uint8_t*>(a) + (lo - sb);
+    if (src == dst) continue;   // decoded in place
+    for (uint64_t q = threadIdx.x; q < hi - lo; q += blockDim.x) dst[q] = src[q];
+  }
+}
+
+}  // namespace
+
+int lz_launch_requests(lz_handle* h, const lz_request* d_reqs, const uint32_t* d_n, uint64_t n_max,
+                       uint64_t single_off, uint64_t single_len, const int64_t* d_ids,
+                       uint8_t* d_out, uint64_t cap, uint64_t* d_offsets, void* d_scratch,
+                       uint64_t scratch_len, hipStream_t s) {
+  const ArchiveView& v = h->av;
+  ReqArgs R{};
+  R.arc = v.base;
+  R.n = v.n;
+  R.off_dir = v.off_dir;
+  R.off_dep_ptr = v.off_dep_ptr;
+  R.off_dep_idx = v.off_dep_idx;
+  R.off_ridx = v.kind == 1 ? v.off_ridx : 0;
+  R.n_reads = v.n_reads;
+  R.bl = v.block_log2;
+  R.mode = d_reqs ? 2u : (d_ids ? 1u : 0u);
+  R.a0 = single_off;
+  R.b0 = single_len;
+  R.ids = d_ids;
+  R.reqs = d_reqs;
+  R.d_n = d_n;
+  R.n_max = n_max;
+  R.out = d_out;
+  R.cap = cap;
+  R.offsets = d_offsets;
+  // scratch: spans, block-count prefix, output prefix, then 16 KiB slots
+  const uint64_t B = 1ull << v.block_log2;
+  uint8_t* sc = reinterpret_cast<uint8_t*>(d_scratch);
+  if (!sc || ((uintptr_t)sc & 255)) return lz_fail(LZ_EINVAL, "request scratch must be 256-byte aligned");
+  const uint64_t spans_b = 16 * n_max, ptr_b = 8 * (n_max + 1);
+  const uint64_t slots_off = (spans_b + 2 * ptr_b + 255) & ~255ull;
+  if (scratch_len < slots_off) return lz_fail(LZ_ECAPACITY, "request scratch needs at least %llu bytes", (unsigned long long)slots_off);
+  R.spans = reinterpret_cast<uint64_t*>(sc);
+  R.cnt_ptr = reinterpret_cast<uint64_t*>(sc + spans_b);
+  R.offs = reinterpret_cast<uint64_t*>(sc + spans_b + ptr_b);
+  R.slots = sc + slots_off;
+  R.max_slots = (scratch_len - slots_off) / B;
+  R.direct = (R.mode == 0 && ((uintptr_t)d_out & 15) == 0) ? 1u : 0u;
+  R.mark = h->ws.mark;
+  R.addr = h->ws.addr;
+  R.rqueue = h->ws.rqueue;
+  R.rlevel_ptr = h->ws.rlevel_ptr;
+  R.list = h->ws.list;
+  R.ctl = h->ws.ctl;
+  const uint32_t spin = h->tune.spin_limit ? h->tune.spin_limit : (1u << 20);
+  const uint32_t g_req = (uint32_t)std::min<uint64_t>(1024, (n_max + 255) / 256);
+  const uint32_t g_wide = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(1024, (v.n_blocks + 255) / 256));
+  hipLaunchKernelGGL(k_req_begin, dim3(1), dim3(64), 0, s, R);
+  hipLaunchKernelGGL(k_req_spans, dim3(g_req), dim3(256), 0, s, R);
+  hipLaunchKernelGGL(k_req_scan, dim3(1), dim3(1024), 0, s, R);
+  hipLaunchKernelGGL(k_req_mark, dim3(g_wide), dim3(256), 0, s, R);
+  hipLaunchKernelGGL(k_closure, dim3(std::min<uint32_t>(64, g_wide)), dim3(256), 0, s, R, spin);
+  hipLaunchKernelGGL(k_req_levels, dim3(g_wide), dim3(256), 0, s, R);
+  hipLaunchKernelGGL(k_req_level_scan, dim3(1), dim3(64), 0, s, R);
+  hipLaunchKernelGGL(k_req_scatter, dim3(g_wide), dim3(256), 0, s, R);
+  // decode the closure in level order (persistent, or one launch per level)
+  DevArgs A = make_args(h);
+  A.queue = h->ws.rqueue;
+  A.qptr = h->ws.rlevel_ptr;
+  A.addr = h->ws.addr;
+  A.out = d_out;
+  const uint32_t slots = (uint32_t)(h->n_cu * std::max(1u, h->tune.wg_per_cu));
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(slots, std::max<uint64_t>(1, v.n_blocks));
+  if (h->tune.sync_mode == 1) {
+    A.persistent = 1;
+    A.q_begin = 0;
+    A.q_end = 64;
+    hipLaunchKernelGGL(k_decode, dim3(grid), dim3(kWG), 0, s, A);
+  } else {
+    for (uint32_t L = 0; L < v.n_levels; L++) {
+      A.q_begin = L;
+      A.q_end = L + 1;
+      hipLaunchKernelGGL(k_decode, dim3(grid), dim3(kWG), 0, s, A);
+    }
+  }
+  hipLaunchKernelGGL(k_req_gather, dim3(g_wide), dim3(256), 0, s, R);
+  return launch_ok("request decode");
 }

@@ -53,26 +53,26 @@ struct Workspace {
   uint32_t* mark;         // n_blocks: request epoch per block (closure)
   uint64_t* addr;         // n_blocks: device address of decoded block bytes
   uint32_t* rqueue;       // n_blocks: request closure queue (level order)
-  uint32_t* rlevel_ptr;   // 65 + 65: level offsets / cursors of rqueue
-  uint32_t* frontier;     // 2 * n_blocks: closure work lists
+  uint32_t* rlevel_ptr;   // 65 level offsets + 64 cursors of rqueue
+  uint64_t* list;         // n_blocks: closure work list, entries (epoch << 32 | block)
   uint32_t* ctl;          // control words (see kCtl*)
-  uint64_t* req_span;     // per request [start, end) bytes (2 * max_req)
-  uint64_t max_req;
 };
 
-// control words in Workspace::ctl
+// control words in Workspace::ctl (u32 each; 64-bit values use two words)
 enum : uint32_t {
   kCtlStatus = 0,     // latched status bits
   kCtlTicket = 1,     // persistent-kernel ticket counter
-  kCtlEpoch = 2,      // completion epoch (flags)
-  kCtlREpoch = 3,     // request epoch (marks)
-  kCtlClosure = 4,    // number of blocks in the request closure
-  kCtlSlots = 5,      // scratch slots used
-  kCtlFront0 = 6,     // frontier sizes
-  kCtlFront1 = 7,
-  kCtlTotalLo = 8,    // total output bytes of a request batch (u64)
-  kCtlTotalHi = 9,
-  kCtlWords = 16,
+  kCtlEpoch = 2,      // completion epoch (per-block flags)
+  kCtlREpoch = 3,     // request epoch (closure marks)
+  kCtlListTail = 4,   // closure list: entries pushed
+  kCtlListHead = 5,   // closure list: entries taken
+  kCtlListDone = 6,   // closure list: entries fully expanded
+  kCtlSlots = 7,      // scratch slots handed out
+  kCtlNReq = 8,       // number of requests of the current batch
+  kCtlTotal = 10,     // u64: total output bytes of the batch
+  kCtlPairs = 12,     // u64: (request, covering block) pairs of the batch
+  kCtlLevelCnt = 16,  // 64 level counters of the closure queue
+  kCtlWords = 96,
 };
 
 struct lz_handle {

@@ -96,7 +96,7 @@ int parse_header(const uint8_t* a, uint64_t len, ArchiveView& v, uint64_t& total
 }
 
 struct Layout {
-  uint64_t lut, queue, level_ptr, flags, mark, addr, rqueue, rlevel_ptr, frontier, ctl, total;
+  uint64_t lut, queue, level_ptr, flags, mark, addr, rqueue, rlevel_ptr, list, ctl, total;
 };
 
 Layout layout_for(uint64_t nb) {
@@ -111,7 +111,7 @@ Layout layout_for(uint64_t nb) {
   L.addr = take(8 * std::max<uint64_t>(nb, 1));
   L.rqueue = take(4 * std::max<uint64_t>(nb, 1));
   L.rlevel_ptr = take(4 * 130);
-  L.frontier = take(8 * std::max<uint64_t>(nb, 1));
+  L.list = take(8 * std::max<uint64_t>(nb, 1));
   L.ctl = take(4 * kCtlWords);
   L.total = o;
   return L;
@@ -254,13 +254,13 @@ extern "C" int lz_open(const uint8_t* d_archive, uint64_t len, void* d_ws, uint6
   h->ws.addr = (uint64_t*)(w + L.addr);
   h->ws.rqueue = (uint32_t*)(w + L.rqueue);
   h->ws.rlevel_ptr = (uint32_t*)(w + L.rlevel_ptr);
-  h->ws.frontier = (uint32_t*)(w + L.frontier);
+  h->ws.list = (uint64_t*)(w + L.list);
   h->ws.ctl = (uint32_t*)(w + L.ctl);
   std::memcpy(h->level_count, count, sizeof(count));
   h->literal_bytes = lit_total;
   h->payload_bytes = prev_end;
   h->tune.sync_mode = 1;
-  h->tune.wg_per_cu = 2;
+  h->tune.wg_per_cu = 3;
   h->tune.spin_limit = 0;
   int dev = 0;
   hipDeviceProp_t prop;

@@ -60,6 +60,10 @@ def test_lanes_rule(orc):
     assert orc.rans_lanes(16000, 256) == 256
     assert orc.rans_lanes(16000, 100) == 100
     assert orc.rans_lanes(1000, 256) == 32
+    # short streams: 4 symbols per lane
+    assert orc.rans_lanes(3, 64, 4) == 1
+    assert orc.rans_lanes(120, 64, 4) == 16
+    assert orc.rans_lanes(4100, 64, 4) == 64
 
 
 def _streams():
