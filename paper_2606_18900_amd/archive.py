@@ -166,6 +166,29 @@ class Archive:
         check(lib().lz_decode_batch(self.h, _ptr(reqs), _ptr(n), n_max, _ptr(out), out.numel(),
                                     _ptr(offsets), _ptr(scratch), scratch.numel(), _stream(stream)))
 
+    def stream_range(self, offset: int, length: int, window: int,
+                     out: torch.Tensor | None = None, scratch: torch.Tensor | None = None,
+                     stream=None):
+        """Range decode through a capped output window (Scale section: output
+        larger than device memory).  Yields (window_offset, view) for consecutive
+        windows of at most `window` bytes decoded into the same buffer; each
+        view is valid until the next one is produced (the caller synchronises or
+        consumes on the same stream).  Blocks an earlier window already dropped
+        are decoded again into scratch when a later block needs them."""
+        if out is None:
+            out = torch.empty(window, dtype=torch.uint8, device=self.device)
+        assert out.numel() >= window
+        if scratch is None:
+            scratch = self._scratch(1, scratch, n_slots=min(self.n_blocks, 65536))
+        o = offset
+        end = offset + length
+        while o < end:
+            w = min(window, end - o)
+            check(lib().lz_decode_range(self.h, o, w, _ptr(out), _ptr(scratch), scratch.numel(),
+                                        _stream(stream)))
+            yield o, out[:w]
+            o += w
+
     def verify(self, out: torch.Tensor, stream=None) -> torch.Tensor:
         tree = torch.zeros(1, dtype=torch.int64, device=self.device)
         scratch = torch.empty(max(8 * self.n_blocks, 8), dtype=torch.uint8, device=self.device)

@@ -162,3 +162,32 @@ def test_request_errors(fq, lz):
         _sync(arc)
     assert e.value.code == lz._lib.LZ_ECAPACITY
     assert _range(arc, 0, 1000) == x[:1000]      # still usable afterwards
+
+
+def test_batcher_graph_replays(fq):
+    """A captured batch graph replayed several times with different request
+    contents, eager work and synchronisation in between: every replay equals
+    the eager (ungraphed) result and the plain definition."""
+    from paper_2606_18900_amd.batch import Batcher
+    x, starts, arc = fq
+    arc.set_tuning(sync_mode=1)
+    rng = np.random.default_rng(5)
+    g = Batcher(arc, n_max=256, out_cap=8 << 20, use_graph=True)
+    e = Batcher(arc, n_max=256, out_cap=8 << 20, use_graph=False)
+    for rep in range(4):
+        k = int(rng.integers(1, 257))
+        kind = (rng.random(k) < 0.2).astype(np.int64)
+        a = np.where(kind == 0, rng.integers(0, len(starts) - 1, k), rng.integers(0, len(x) - 70000, k))
+        b = np.where(kind == 0, 0, rng.integers(1, 65536, k))
+        g.submit(kind, a, b)
+        got = g.results()
+        e.submit(kind, a, b)
+        ref = e.results()
+        assert got == ref
+        for kk, aa, bb, gg in zip(kind, a, b, got):
+            exp = x[int(starts[aa]):int(starts[aa + 1])] if kk == 0 else x[aa:aa + bb]
+            assert gg == exp
+        # unrelated eager work on the device between replays
+        torch.cuda.synchronize()
+        arc.decode_range(100, 5000)
+        _sync(arc)
