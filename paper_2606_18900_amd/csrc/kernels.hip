@@ -840,7 +840,10 @@ __global__ void k_req_mark(ReqArgs R) {
 
 // Transitive closure over the dependency lists with a shared worklist.  Each
 // thread takes list entries in turn; it stops when every pushed entry has
-// been expanded (done == tail read in that order: no entry can appear later).
+// been expanded.  An entry's expansion pushes its children (tail) before it
+// counts itself done with release order; a reader loads done with acquire
+// order and then tail, so done == tail means no entry is in flight and none
+// can appear later.
 __global__ void k_closure(ReqArgs R, uint32_t spin_limit) {
   const uint32_t epoch = aload(R.ctl + kCtlREpoch);
   for (;;) {
@@ -848,7 +851,7 @@ __global__ void k_closure(ReqArgs R, uint32_t spin_limit) {
     uint32_t spins = 0;
     for (;;) {
       if (i < aload(R.ctl + kCtlListTail)) break;
-      const uint32_t done = aload(R.ctl + kCtlListDone);
+      const uint32_t done = __hip_atomic_load(R.ctl + kCtlListDone, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
       if (done == aload(R.ctl + kCtlListTail) && i >= done) return;
       if (++spins > spin_limit) { latch(R.ctl, kStWatchdog); return; }
       __builtin_amdgcn_s_sleep(1);
@@ -862,7 +865,7 @@ __global__ void k_closure(ReqArgs R, uint32_t spin_limit) {
     const uint32_t b = (uint32_t)v;
     const uint64_t d0 = ld64(R.arc + R.off_dep_ptr + 8ull * b), d1 = ld64(R.arc + R.off_dep_ptr + 8ull * (b + 1));
     for (uint64_t k = d0; k < d1; k++) mark_push(R, ld32(R.arc + R.off_dep_idx + 4 * k), epoch);
-    __hip_atomic_fetch_add(R.ctl + kCtlListDone, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(R.ctl + kCtlListDone, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 

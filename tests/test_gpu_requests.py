@@ -61,6 +61,7 @@ def test_range_edges_small_blocks(small):
     cases += [(int(o), int(rng.integers(1, min(4000, N - o) + 1))) for o in rng.integers(0, N - 1, 30)]
     for mode in (1, 0):
         for o, L in cases:
+            print("range case", o, L, "mode", mode, flush=True)
             assert _range(arc, o, L, mode) == x[o:o + L], (o, L, mode)
 
 
