@@ -81,6 +81,18 @@ __device__ __forceinline__ void latch(uint32_t* ctl, uint32_t bits) {
   __hip_atomic_fetch_or(ctl + kCtlStatus, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Watchdog: latch the status bit and, for the first one, what was waited on
+// (site 1 = decode dependency flag, 2 = closure entry, 3 = closure end).
+__device__ __forceinline__ void watchdog(uint32_t* ctl, uint32_t site, uint32_t a, uint32_t b,
+                                         uint32_t seen, uint32_t want) {
+  if (__hip_atomic_fetch_or(ctl + kCtlStatus, kStWatchdog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kStWatchdog) return;
+  ctl[kCtlDiag + 0] = site;
+  ctl[kCtlDiag + 1] = a;
+  ctl[kCtlDiag + 2] = b;
+  ctl[kCtlDiag + 3] = seen;
+  ctl[kCtlDiag + 4] = want;
+}
+
 // One stream record, parsed by every thread from global memory (uniform).
 struct Stream {
   uint32_t mode, csym, K, n, nw, blen, body;
@@ -477,9 +489,10 @@ __global__ void __launch_bounds__(kWG) k_decode(DevArgs A) {
     const uint64_t d1 = ld64(A.arc + A.off_dep_ptr + 8ull * (b + 1));
     for (uint64_t k = d0 + t; k < d1; k += kWG) {
       const uint32_t d = ld32(A.arc + A.off_dep_idx + 4 * k);
+      uint32_t f;
       for (uint32_t spins = 0;
-           __hip_atomic_load(A.flags + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch; spins++) {
-        if (spins >= A.spin_limit) { latch(A.ctl, kStWatchdog); break; }
+           (f = __hip_atomic_load(A.flags + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != epoch; spins++) {
+        if (spins >= A.spin_limit) { watchdog(A.ctl, 1, b, d, f, epoch); break; }
         __builtin_amdgcn_s_sleep(1);
       }
     }
@@ -853,13 +866,13 @@ __global__ void k_closure(ReqArgs R, uint32_t spin_limit) {
       if (i < aload(R.ctl + kCtlListTail)) break;
       const uint32_t done = __hip_atomic_load(R.ctl + kCtlListDone, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
       if (done == aload(R.ctl + kCtlListTail) && i >= done) return;
-      if (++spins > spin_limit) { latch(R.ctl, kStWatchdog); return; }
+      if (++spins > spin_limit) { watchdog(R.ctl, 3, i, done, aload(R.ctl + kCtlListTail), epoch); return; }
       __builtin_amdgcn_s_sleep(1);
     }
     uint64_t v;
     spins = 0;
     while (((v = __hip_atomic_load(R.list + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 32) != epoch) {
-      if (++spins > spin_limit) { latch(R.ctl, kStWatchdog); return; }
+      if (++spins > spin_limit) { watchdog(R.ctl, 2, i, (uint32_t)v, (uint32_t)(v >> 32), epoch); return; }
       __builtin_amdgcn_s_sleep(1);
     }
     const uint32_t b = (uint32_t)v;

@@ -72,6 +72,7 @@ enum : uint32_t {
   kCtlTotal = 10,     // u64: total output bytes of the batch
   kCtlPairs = 12,     // u64: (request, covering block) pairs of the batch
   kCtlLevelCnt = 16,  // 64 level counters of the closure queue
+  kCtlDiag = 80,      // first watchdog: site, block, dependency, seen, expected
   kCtlWords = 96,
 };
 

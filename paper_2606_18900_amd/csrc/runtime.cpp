@@ -335,13 +335,20 @@ extern "C" int lz_sync_status(lz_handle* h, hipStream_t s) {
   if (!rc) rc = hip_check(hipStreamSynchronize(s), "lz_sync_status: sync");
   if (rc) return rc;
   if (!st) return LZ_OK;
-  uint32_t zero = 0;
-  rc = hip_check(hipMemcpyAsync(h->ws.ctl + kCtlStatus, &zero, 4, hipMemcpyHostToDevice, s), "lz_sync_status: clear");
+  uint32_t diag[5] = {0, 0, 0, 0, 0};
+  rc = hip_check(hipMemcpyAsync(diag, h->ws.ctl + kCtlDiag, sizeof(diag), hipMemcpyDeviceToHost, s), "lz_sync_status: copy");
+  if (!rc) rc = hip_check(hipStreamSynchronize(s), "lz_sync_status: sync");
+  if (rc) return rc;
+  uint32_t zero[6] = {0, 0, 0, 0, 0, 0};
+  rc = hip_check(hipMemcpyAsync(h->ws.ctl + kCtlDiag, zero, sizeof(diag), hipMemcpyHostToDevice, s), "lz_sync_status: clear");
+  if (!rc) rc = hip_check(hipMemcpyAsync(h->ws.ctl + kCtlStatus, zero, 4, hipMemcpyHostToDevice, s), "lz_sync_status: clear");
   if (!rc) rc = hip_check(hipStreamSynchronize(s), "lz_sync_status: sync");
   if (rc) return rc;
   if (st & kStRange) return lz_fail(LZ_ERANGE, "device: request out of range (status 0x%x)", st);
   if (st & kStCapacity) return lz_fail(LZ_ECAPACITY, "device: scratch or output capacity exhausted (status 0x%x)", st);
-  if (st & kStWatchdog) return lz_fail(LZ_ECORRUPT, "device: dependency wait timed out (status 0x%x)", st);
+  if (st & kStWatchdog)
+    return lz_fail(LZ_ECORRUPT, "device: wait timed out (status 0x%x; site %u, %u, %u, seen %u, expected %u)", st,
+                   diag[0], diag[1], diag[2], diag[3], diag[4]);
   return lz_fail(LZ_ECORRUPT, "device: decode check failed (status 0x%x)", st);
 }
 

@@ -43,12 +43,45 @@ def small(orc, lz):
     return x, lz.Archive(a)
 
 
+def _ws_view(arc):
+    # workspace sections, in lz_open's order (256-byte aligned)
+    nb = arc.n_blocks
+    sizes = [("lut", 4096 * 4), ("queue", 4 * nb), ("level_ptr", 4 * 65), ("flags", 4 * nb),
+             ("mark", 4 * nb), ("addr", 8 * nb), ("rqueue", 4 * nb), ("rlevel_ptr", 4 * 130),
+             ("list", 8 * nb), ("ctl", 4 * 96)]
+    ws = arc.ws.cpu().numpy()
+    out, o = {}, 0
+    for name, sz in sizes:
+        out[name] = ws[o:o + sz]
+        o = (o + sz + 255) & ~255
+    return out
+
+
+def _diagnose(arc):
+    w = _ws_view(arc)
+    nb = arc.n_blocks
+    ctl = w["ctl"].view(np.uint32)
+    rq = w["rqueue"].view(np.uint32)
+    rl = w["rlevel_ptr"].view(np.uint32)
+    fl = w["flags"].view(np.uint32)
+    print("ctl", ctl[:16].tolist(), "diag", ctl[80:85].tolist())
+    print("rlevel_ptr", rl[:65].tolist())
+    n = int(rl[64])
+    print("queue is permutation:", sorted(rq[:n].tolist()) == list(range(nb)), "n", n, "nb", nb)
+    print("flags != epoch:", np.flatnonzero(fl[:nb] != ctl[2]).tolist()[:20])
+
+
 def _range(arc, o, L, mode=1):
     arc.set_tuning(sync_mode=mode)
     out = torch.empty(max(L, 1) + 64, dtype=torch.uint8, device="cuda")
     scratch = torch.full((arc.scratch_bytes(1),), 0xAA, dtype=torch.uint8, device="cuda")
     arc.decode_range(o, L, out=out, scratch=scratch)
-    _sync(arc)
+    torch.cuda.synchronize()
+    try:
+        arc.sync_status()
+    except Exception:
+        _diagnose(arc)
+        raise
     return out[:L].cpu().numpy().tobytes()
 
 
