@@ -851,34 +851,55 @@ __global__ void k_req_mark(ReqArgs R) {
   }
 }
 
-// Transitive closure over the dependency lists with a shared worklist.  Each
-// thread takes list entries in turn; it stops when every pushed entry has
-// been expanded.  An entry's expansion pushes its children (tail) before it
-// counts itself done with release order; a reader loads done with acquire
-// order and then tail, so done == tail means no entry is in flight and none
-// can appear later.
+// Transitive closure over the dependency lists with a shared worklist.
+// Control flow is uniform per wave (lanes of a wave cannot wait for each
+// other): a wave takes 64 consecutive list indices, expands those already
+// pushed (tail), and keeps the rest pending.  An expansion pushes the block's
+// unmarked dependencies and then counts itself done with release order; with
+// nothing ready, the wave loads done with acquire order and then tail: done ==
+// tail means no entry is in flight and none can appear, so the pending indices
+// stay empty and the wave stops.
 __global__ void k_closure(ReqArgs R, uint32_t spin_limit) {
+  const uint32_t lane = lane_id();
   const uint32_t epoch = aload(R.ctl + kCtlREpoch);
   for (;;) {
-    const uint32_t i = __hip_atomic_fetch_add(R.ctl + kCtlListHead, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t i0 = 0;
+    if (lane == 0) i0 = __hip_atomic_fetch_add(R.ctl + kCtlListHead, 64u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    i0 = __shfl(i0, 0, 64);
+    const uint32_t i = i0 + lane;
+    bool pending = true;
     uint32_t spins = 0;
-    for (;;) {
-      if (i < aload(R.ctl + kCtlListTail)) break;
-      const uint32_t done = __hip_atomic_load(R.ctl + kCtlListDone, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-      if (done == aload(R.ctl + kCtlListTail) && i >= done) return;
-      if (++spins > spin_limit) { watchdog(R.ctl, 3, i, done, aload(R.ctl + kCtlListTail), epoch); return; }
+    while (__ballot(pending)) {
+      const uint32_t tail = __shfl(aload(R.ctl + kCtlListTail), 0, 64);
+      const bool ready = pending && i < tail;
+      if (__ballot(ready)) {
+        if (ready) {
+          uint64_t v;
+          uint32_t sp = 0;
+          while (((v = __hip_atomic_load(R.list + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 32) != epoch) {
+            if (++sp > spin_limit) { watchdog(R.ctl, 2, i, (uint32_t)v, (uint32_t)(v >> 32), epoch); break; }
+            __builtin_amdgcn_s_sleep(1);
+          }
+          const uint32_t b = (uint32_t)v;
+          if ((v >> 32) == epoch) {
+            const uint64_t d0 = ld64(R.arc + R.off_dep_ptr + 8ull * b), d1 = ld64(R.arc + R.off_dep_ptr + 8ull * (b + 1));
+            for (uint64_t k = d0; k < d1; k++) mark_push(R, ld32(R.arc + R.off_dep_idx + 4 * k), epoch);
+          }
+          __hip_atomic_fetch_add(R.ctl + kCtlListDone, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          pending = false;
+        }
+        spins = 0;
+        continue;
+      }
+      const uint32_t done = __shfl(__hip_atomic_load(R.ctl + kCtlListDone, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT), 0, 64);
+      const uint32_t tail2 = __shfl(aload(R.ctl + kCtlListTail), 0, 64);
+      if (done == tail2 && !__ballot(pending && i < tail2)) return;   // pending indices past the end
+      if (++spins > spin_limit) {
+        if (lane == 0) watchdog(R.ctl, 3, i0, done, tail2, epoch);
+        return;
+      }
       __builtin_amdgcn_s_sleep(1);
     }
-    uint64_t v;
-    spins = 0;
-    while (((v = __hip_atomic_load(R.list + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 32) != epoch) {
-      if (++spins > spin_limit) { watchdog(R.ctl, 2, i, (uint32_t)v, (uint32_t)(v >> 32), epoch); return; }
-      __builtin_amdgcn_s_sleep(1);
-    }
-    const uint32_t b = (uint32_t)v;
-    const uint64_t d0 = ld64(R.arc + R.off_dep_ptr + 8ull * b), d1 = ld64(R.arc + R.off_dep_ptr + 8ull * (b + 1));
-    for (uint64_t k = d0; k < d1; k++) mark_push(R, ld32(R.arc + R.off_dep_idx + 4 * k), epoch);
-    __hip_atomic_fetch_add(R.ctl + kCtlListDone, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
