@@ -359,10 +359,19 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
       const uint64_t of = (uint64_t)S.oflo[q] | ((uint64_t)S.ofhi[q] << 32);
       const uint32_t d0 = S.out[q] + L;
       if (of + M <= sb) {
-        for (uint32_t k = lane; k < M && d0 + k < blen; k += 64) S.tile[d0 + k] = (uint8_t)src_byte(A, of + k, bad);
-      } else if (lane == 0) {
-        const uint32_t slot = atomicAdd(&S.nint, 1u);
-        if (slot < kMaxSeq) S.intl[slot] = (uint16_t)q;
+        for (uint32_t k0 = 0; k0 < M; k0 += 256) {   // four independent loads in flight
+          uint32_t v[4];
+#pragma unroll
+          for (uint32_t u = 0; u < 4; u++) {
+            const uint32_t k = k0 + 64 * u + lane;
+            v[u] = k < M ? src_byte(A, of + k, bad) : 0u;
+          }
+#pragma unroll
+          for (uint32_t u = 0; u < 4; u++) {
+            const uint32_t k = k0 + 64 * u + lane;
+            if (k < M && d0 + k < blen) S.tile[d0 + k] = (uint8_t)v[u];
+          }
+        }
       }
     }
     if (bad) S.err = 1;
@@ -373,46 +382,113 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
     return;
   }
 
-  // ---- stage 4: matches touching the block itself, in sequence order (wave 0).
+  // ---- stage 4: matches whose source touches the block itself.
   // With period d = p - OF, out[p+k] = out[OF + (k mod d)] for every k (the
-  // byte-sequential overlap rule unrolled), and OF..OF+d-1 are final before the
-  // match starts, so all bytes of one match are copied at once, 64 per step.
+  // byte-sequential overlap rule unrolled); only the window OF..OF+min(d,M)-1
+  // is read and it is final once every earlier match writing into it is done.
+  // 4a: ordered list of these matches (ballot compaction, wave 0);
+  // 4b: per match: destination, length, source (block-relative), period and
+  //     whether its window meets an earlier such match's destination
+  //     (binary search over the sorted destinations), packed into the
+  //     sequence tables, which are no longer needed;
+  // 4c: independent matches copied by all waves in parallel;
+  // 4d: dependent matches copied in order by wave 0.
   if (wv == 0) {
-    const uint32_t cnt = min(S.nint, ns);
-    if (lane == 0)
-      for (uint32_t a = 1; a < cnt; a++) {
-        const uint16_t v = S.intl[a];
-        uint32_t c = a;
-        while (c > 0 && S.intl[c - 1] > v) { S.intl[c] = S.intl[c - 1]; c--; }
-        S.intl[c] = v;
+    uint32_t base = 0;
+    for (uint32_t q0 = 0; q0 < ns; q0 += 64) {
+      const uint32_t q = q0 + lane;
+      bool in = false;
+      if (q < ns) {
+        const uint32_t L = (uint32_t)S.lit[q + 1] - S.lit[q];
+        const uint32_t M = (uint32_t)S.out[q + 1] - S.out[q] - L;
+        const uint64_t of = (uint64_t)S.oflo[q] | ((uint64_t)S.ofhi[q] << 32);
+        in = M && of + M > sb;
       }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    bool bad = false;
-    for (uint32_t a = 0; a < cnt; a++) {
+      const uint64_t bal = __ballot(in);
+      if (in) S.intl[base + mbcnt(bal)] = (uint16_t)q;
+      base += (uint32_t)__popcll(bal);
+    }
+    if (lane == 0) S.nint = base;
+  }
+  __syncthreads();
+  const uint32_t cnt = min(S.nint, ns);
+  {
+    // 4b phase 1: per match in registers (at most 5 per thread)
+    uint32_t md0[5], mM[5], ms[5], md[5];
+    const uint32_t per = (cnt + kWG - 1) / kWG, a0 = min(cnt, t * per), a1 = min(cnt, a0 + per);
+    for (uint32_t a = a0, u = 0; a < a1; a++, u++) {
       const uint32_t q = min((uint32_t)S.intl[a], ns - 1);
       const uint32_t L = (uint32_t)S.lit[q + 1] - S.lit[q];
       const uint32_t M = min((uint32_t)S.out[q + 1] - S.out[q] - L, blen);
       const uint32_t d0 = S.out[q] + L;
       const uint64_t of = (uint64_t)S.oflo[q] | ((uint64_t)S.ofhi[q] << 32);
       const uint64_t dabs = sb + d0;
-      const uint32_t d = dabs > of ? (dabs - of < kB ? (uint32_t)(dabs - of) : kB) : 1u;
-      uint32_t r = lane % d;               // (c + lane) mod d, kept incrementally
+      md0[u] = d0;
+      mM[u] = M;
+      // of >= sb - M here (the source overlaps the block), so the relative
+      // source fits in [-16384, 16384)
+      ms[u] = (uint32_t)((int64_t)of - (int64_t)sb + 16384) & 0xFFFFu;
+      md[u] = dabs > of ? (uint32_t)min<uint64_t>(dabs - of, 32767) : 1u;
+    }
+    __syncthreads();
+    for (uint32_t a = a0, u = 0; a < a1; a++, u++) {
+      S.lit[a] = (uint16_t)md0[u];
+      S.out[a] = (uint16_t)mM[u];
+    }
+    __syncthreads();
+    // 4b phase 2: dependency test against earlier destinations
+    for (uint32_t a = a0, u = 0; a < a1; a++, u++) {
+      const int32_t s = (int32_t)ms[u] - 16384;
+      const uint32_t w = min(md[u], mM[u]);
+      bool dep = false;
+      if (s + (int32_t)w > 0) {
+        const uint32_t ws = s > 0 ? (uint32_t)s : 0u, we = (uint32_t)(s + (int32_t)w);
+        // first earlier match whose destination ends after ws
+        uint32_t lo = 0, hi = a;
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if ((uint32_t)S.lit[mid] + S.out[mid] > ws) hi = mid; else lo = mid + 1;
+        }
+        dep = lo < a && S.lit[lo] < we;
+      }
+      S.oflo[a] = ms[u] | (md[u] << 16) | (dep ? 0x80000000u : 0u);
+    }
+  }
+  __syncthreads();
+  {
+    bool bad = false;
+    auto copy_match = [&](uint32_t a) {
+      const uint32_t pk = S.oflo[a];
+      const uint32_t d0 = S.lit[a], M = S.out[a];
+      const int32_t s = (int32_t)(pk & 0xFFFFu) - 16384;
+      const uint32_t d = (pk >> 16) & 0x7FFFu;
+      uint32_t r = lane % d;                // (c + lane) mod d, kept incrementally
       const uint32_t r64 = 64u % d;
       for (uint32_t c = 0; c < M; c += 64) {
         const uint32_t k = c + lane;
         if (k < M && d0 + k < blen) {
-          const uint64_t s = of + r;
-          const uint32_t v = s >= sb ? (uint32_t)S.tile[(uint32_t)(s - sb) & (kB - 1)] : src_byte(A, s, bad);
+          const int32_t src = s + (int32_t)r;
+          const uint32_t v = src >= 0 ? (uint32_t)S.tile[(uint32_t)src & (kB - 1)]
+                                      : src_byte(A, sb + (int64_t)src, bad);
           S.tile[d0 + k] = (uint8_t)v;
         }
         r += r64;
         if (r >= d) r -= d;
       }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-    }
-    if (bad && lane == 0) S.err = 1;
+    };
+    // 4c: independent matches, all waves
+    for (uint32_t a = wv; a < cnt; a += kWaves)
+      if (!(S.oflo[a] & 0x80000000u)) copy_match(a);
+    __syncthreads();
+    // 4d: dependent matches in order, wave 0 (LDS operations of one wave are
+    // performed in order, so each copy sees the previous ones)
+    if (wv == 0)
+      for (uint32_t a = 0; a < cnt; a++)
+        if (S.oflo[a] & 0x80000000u) {
+          copy_match(a);
+          __builtin_amdgcn_wave_barrier();
+        }
+    if (bad) S.err = 1;
   }
   __syncthreads();
   if (S.err) {
