@@ -25,6 +25,15 @@ FASTQ_PARAMS = dict(kind=1, block_log2=14, max_level=64, min_match=16, hash_len=
                     seq_lanes=64, prob_bits=(12, 10, 10, 10), level_penalty=32)
 HBM_PEAK_GBPS = 8000.0      # MI355X HBM3E
 
+# HBM bytes moved by one whole-file decode of the 1 GiB archive (per-level
+# launches), from two rocprofv3 --pmc runs of `bench.py --legs decode`
+# (FETCH_SIZE, then WRITE_SIZE, summed over the k_decode dispatches of a
+# decode), each scaled by what the same counter reads for a 1 GiB device copy
+# (`bench.py --legs copy`: FETCH_SIZE x 1.99995, WRITE_SIZE x 1.0).  Reported
+# only while the decoder source is the one the counters were taken on.
+PMC_TRAFFIC = {"kernels_sha256_16": "9742c0bdb7d3af40", "bytes": 1 << 30,
+               "fetch": 598863044, "write": 1074796256}
+
 
 def log(msg: str) -> None:
     print("[bench] " + msg, file=sys.stderr, flush=True)
@@ -36,6 +45,87 @@ def host_threads() -> int:
     return max(1, min(n, int(env))) if env else n
 
 
+def pct(v, q):
+    import numpy as np
+    return round(float(np.percentile(np.asarray(v), q)), 1)
+
+
+def read_latency(arc, starts, n, dev):
+    """Single-read lookups, one lz_read_lookup per read (closure, level-ordered
+    decode of the closure, gather): device time between events around the call
+    on its stream, and host time from the call to completion."""
+    import numpy as np
+    import torch
+    from gen.requests import read_ids
+    rng = np.random.default_rng(4)
+    ids = torch.as_tensor(read_ids(rng, len(starts) - 1, n), device=dev)
+    out = torch.empty(int(arc.info.max_record_len), dtype=torch.uint8, device=dev)
+    offs = torch.empty(2, dtype=torch.int64, device=dev)
+    scr = arc._scratch(1, None, n_slots=4096)
+    stream = torch.cuda.current_stream()
+    for k in range(20):                                  # warm-up
+        arc.read_lookup(ids[k:k + 1], out, offs, scr)
+    torch.cuda.synchronize()
+    dev_us, wall_us = [], []
+    for k in range(n):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        arc.read_lookup(ids[k:k + 1], out, offs, scr)
+        e1.record(stream)
+        e1.synchronize()
+        wall_us.append((time.perf_counter() - t0) * 1e6)
+        dev_us.append(e0.elapsed_time(e1) * 1e3)
+    arc.sync_status()
+    return {"n": n, "device_p50_us": pct(dev_us, 50), "device_p99_us": pct(dev_us, 99),
+            "wall_p50_us": pct(wall_us, 50), "wall_p99_us": pct(wall_us, 99),
+            "what": "one read per lz_read_lookup call, ids half uniform half Zipf(1.1)"}
+
+
+def batched_lookups_leg(arc, starts, N, dev, log, src):
+    """2^20 mixed requests (90 % reads, 10 % ranges of 4 KiB..1 MiB) served in
+    batches through one captured HIP graph per batch size; each batch is
+    copied in, replayed and waited for.  Batch size 1 without a graph is the
+    one-launch-sequence-per-request baseline (run on the first 4096 requests)."""
+    import numpy as np
+    import torch
+    from gen.requests import batched_lookups
+    from paper_2606_18900_amd import Batcher
+    kind, a, b = batched_lookups(1 << 20, starts, N, seed=4)
+    rec = np.diff(starts)
+    nbytes = np.where(kind == 0, rec[np.minimum(a, len(rec) - 1)], b)
+    res = {}
+    for bs, use_graph, limit in ((1, False, 4096), (1, True, 4096), (16, True, 1 << 16),
+                                 (256, True, 1 << 20), (4096, True, 1 << 20)):
+        n_req = min(limit, len(kind))
+        nb = n_req // bs
+        cap = int(max(nbytes[q * bs:(q + 1) * bs].sum() for q in range(nb)))
+        bt = Batcher(arc, bs, cap, n_slots=min(arc.n_blocks, 16384), use_graph=use_graph)
+        lat = []
+        t0 = time.perf_counter()
+        for q in range(nb):
+            sl = slice(q * bs, (q + 1) * bs)
+            t1 = time.perf_counter()
+            bt.submit(kind[sl], a[sl], b[sl])
+            bt.stream.synchronize()
+            lat.append((time.perf_counter() - t1) * 1e6)
+        wall = time.perf_counter() - t0
+        got = bt.results()                   # last batch, checked against the source
+        q = nb - 1
+        for j, r in enumerate(range(q * bs, (q + 1) * bs)):
+            o = int(starts[a[r]]) if kind[r] == 0 else int(a[r])
+            if got[j] != src[o:o + int(nbytes[r])]:
+                raise RuntimeError("batched lookup mismatch (batch size %d, request %d)" % (bs, r))
+        key = "batch%d%s" % (bs, "" if use_graph else "_eager")
+        res[key] = {"requests": nb * bs, "req_per_s": round(nb * bs / wall, 1),
+                    "GB_per_s": round(float(nbytes[:nb * bs].sum()) / wall / 1e9, 3),
+                    "batch_p50_us": pct(lat, 50), "batch_p99_us": pct(lat, 99)}
+        log("batched lookups %s: %s" % (key, res[key]))
+        del bt
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -43,6 +133,12 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--bytes", type=int, default=1 << 30, help="FASTQ size (default 1 GiB)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--legs", choices=("all", "decode", "copy"), default="all",
+                    help="decode: only the whole-file decode in the reported launch mode "
+                         "(for profiling; no range leg, no CPU baseline); copy: a plain "
+                         "device-to-device copy of --bytes bytes (counter calibration)")
+    ap.add_argument("--cache", default=None,
+                    help="directory for the encoded archive: reused when present")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the decode path has no "
@@ -55,12 +151,29 @@ def main() -> int:
     import paper_2606_18900_amd as lz
     from gen.fastq import fastq
 
+    if args.legs == "copy":
+        src_d = torch.full((args.bytes,), 7, dtype=torch.uint8, device="cuda")
+        dst_d = torch.empty_like(src_d)
+        for _ in range(args.steps):
+            dst_d.copy_(src_d)
+        torch.cuda.synchronize()
+        log("copied %d bytes %d times" % (args.bytes, args.steps))
+        return 0
     threads = host_threads()
     t0 = time.time()
     x, starts = fastq(max_bytes=args.bytes, seed=2)
     log("generated %d bytes, %d records in %.1f s" % (len(x), len(starts) - 1, time.time() - t0))
     t0 = time.time()
-    a = lz.encode(x, threads=threads, **FASTQ_PARAMS)
+    cached = os.path.join(args.cache, "fastq_%d_seed2.lz" % args.bytes) if args.cache else None
+    if cached and os.path.exists(cached):
+        with open(cached, "rb") as f:
+            a = f.read()
+    else:
+        a = lz.encode(x, threads=threads, **FASTQ_PARAMS)
+        if cached:
+            os.makedirs(args.cache, exist_ok=True)
+            with open(cached, "wb") as f:
+                f.write(a)
     enc_s = time.time() - t0
     log("encoded to %d bytes (ratio %.3f) in %.1f s on %d threads" % (len(a), len(x) / len(a), enc_s, threads))
 
@@ -70,22 +183,24 @@ def main() -> int:
     out = torch.empty(N + 256, dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
 
-    # correctness of the benchmarked configuration (outside the timer)
-    arc.set_tuning(sync_mode=1, wg_per_cu=3)
-    arc.decode_all(out)
-    torch.cuda.synchronize()
-    arc.sync_status()
-    got = out[:N].cpu().numpy()
+    # correctness of both launch modes (outside the timer)
     src = np.frombuffer(x, dtype=np.uint8)
-    if not np.array_equal(got, src):
-        bad = int(np.flatnonzero(got != src)[0])
-        log("MISMATCH at byte %d" % bad)
-        return 1
-    tree = int(arc.verify(out).cpu().item()) & 0xFFFFFFFFFFFFFFFF
-    arc.sync_status()
-    if tree != int(lz.info(a).source_fnv):
-        log("FNV tree mismatch")
-        return 1
+    for mode in ((0,) if args.legs == "decode" else (0, 1)):
+        arc.set_tuning(sync_mode=mode, wg_per_cu=3)
+        out.zero_()
+        arc.decode_all(out)
+        torch.cuda.synchronize()
+        arc.sync_status()
+        got = out[:N].cpu().numpy()
+        if not np.array_equal(got, src):
+            bad = int(np.flatnonzero(got != src)[0])
+            log("MISMATCH (mode %d) at byte %d" % (mode, bad))
+            return 1
+        tree = int(arc.verify(out).cpu().item()) & 0xFFFFFFFFFFFFFFFF
+        arc.sync_status()
+        if tree != int(lz.info(a).source_fnv):
+            log("FNV tree mismatch (mode %d)" % mode)
+            return 1
     log("decoded output bit-exact vs source (%d bytes), device FNV tree ok" % N)
 
     def run(mode: int, wg: int, steps: int, warmup: int):
@@ -106,45 +221,64 @@ def main() -> int:
         ms = [e0.elapsed_time(e1) for e0, e1 in evs]
         return wall, ms
 
-    # baseline: plain per-level launches
-    base_wall, base_ms = run(0, 3, max(3, args.steps // 4), 1)
-    base_gbps = N / (sum(base_ms) / len(base_ms) / 1e3) / 1e9
-    log("per-level launches: %.3f ms/decode, %.1f GB/s" % (np.mean(base_ms), base_gbps))
-    # persistent kernel with completion flags
-    wall, ms = run(1, 3, args.steps, args.warmup)
+    # both launch modes: one launch per dependency level, and one persistent
+    # launch whose workgroups wait on per-block completion flags
+    modes = {}
+    for mode, name in (((0, "per-level launches"),) if args.legs == "decode" else
+                       ((0, "per-level launches"), (1, "persistent"))):
+        wall, ms = run(mode, 3, args.steps, args.warmup)
+        modes[mode] = (wall, ms)
+        log("%s: %.3f ms/decode (events), %.1f GB/s" % (name, np.mean(ms), N / (np.mean(ms) / 1e3) / 1e9))
+    best = min(modes, key=lambda m: np.mean(modes[m][1]))
+    wall, ms = modes[best]
+    other = modes[1 - best][1] if len(modes) > 1 else None
     ms_step = wall * 1e3 / args.steps
     value = N * args.steps / wall / 1e9
     kern_ms = float(np.mean(ms))
-    log("persistent: %.3f ms/step wall, %.3f ms per decode (events), %.1f GB/s" % (ms_step, kern_ms, value))
+    launch = ("one launch per dependency level, 3 workgroups/CU" if best == 0
+              else "persistent, 3 workgroups/CU, per-block completion flags")
+    log("reported: %s, %.3f ms/step wall, %.1f GB/s" % (launch, ms_step, value))
+    arc.set_tuning(sync_mode=best, wg_per_cu=3)
 
+    range_gbps = None
+    if args.legs == "decode":
+        args.no_cpu_baseline = True
     # range leg: the whole file streamed through a capped 256 MiB output window
     # (one lz_decode_range per window; earlier blocks a window needs are
     # decoded again into scratch)
-    win = 256 << 20
-    wbuf = torch.empty(win, dtype=torch.uint8, device=dev)
-    wscr = torch.empty(arc.scratch_bytes(1, 16384), dtype=torch.uint8, device=dev)
-    arc.set_tuning(sync_mode=1, wg_per_cu=3)
-    h_ok = True
-    for o, view in arc.stream_range(0, N, win, out=wbuf, scratch=wscr):
-        got_w = view.cpu().numpy()
-        h_ok = h_ok and np.array_equal(got_w, src[o:o + view.numel()])
-    arc.sync_status()
-    if not h_ok:
-        log("windowed range decode MISMATCH")
-        return 1
-    torch.cuda.synchronize()
-    r0 = torch.cuda.Event(enable_timing=True)
-    r1 = torch.cuda.Event(enable_timing=True)
-    r_steps = max(2, args.steps // 4)
-    r0.record(stream)
-    for _ in range(r_steps):
+    if args.legs == "all":
+        win = 256 << 20
+        wbuf = torch.empty(win, dtype=torch.uint8, device=dev)
+        wscr = torch.empty(arc.scratch_bytes(1, 16384), dtype=torch.uint8, device=dev)
+        h_ok = True
         for o, view in arc.stream_range(0, N, win, out=wbuf, scratch=wscr):
-            pass
-    r1.record(stream)
-    torch.cuda.synchronize()
-    arc.sync_status()
-    range_gbps = N * r_steps / (r0.elapsed_time(r1) / 1e3) / 1e9
-    log("windowed range decode (256 MiB window): %.1f GB/s" % range_gbps)
+            got_w = view.cpu().numpy()
+            h_ok = h_ok and np.array_equal(got_w, src[o:o + view.numel()])
+        arc.sync_status()
+        if not h_ok:
+            log("windowed range decode MISMATCH")
+            return 1
+        torch.cuda.synchronize()
+        r0 = torch.cuda.Event(enable_timing=True)
+        r1 = torch.cuda.Event(enable_timing=True)
+        r_steps = max(2, args.steps // 4)
+        r0.record(stream)
+        for _ in range(r_steps):
+            for o, view in arc.stream_range(0, N, win, out=wbuf, scratch=wscr):
+                pass
+        r1.record(stream)
+        torch.cuda.synchronize()
+        arc.sync_status()
+        range_gbps = N * r_steps / (r0.elapsed_time(r1) / 1e3) / 1e9
+        log("windowed range decode (256 MiB window): %.1f GB/s" % range_gbps)
+
+    read_lat = batch_res = None
+    if args.legs == "all":
+        read_lat = read_latency(arc, starts, 2000, dev)
+        log("single-read lookup latency: device p50 %.1f us p99 %.1f us; call-to-done p50 %.1f us p99 %.1f us"
+            % (read_lat["device_p50_us"], read_lat["device_p99_us"], read_lat["wall_p50_us"],
+               read_lat["wall_p99_us"]))
+        batch_res = batched_lookups_leg(arc, starts, N, dev, log, x)
 
     # algorithmic bytes of one decode: compressed payload + directory +
     # dependency lists read, match-source bytes, output bytes
@@ -154,6 +288,13 @@ def main() -> int:
     match_bytes = N - arc.literal_bytes
     algo = arc.payload_bytes + 32 * nb + dep_bytes + match_bytes + N
     achieved = algo / (kern_ms / 1e3) / 1e9
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2606_18900_amd", "csrc", "kernels.hip"), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    traffic = None
+    if (sha == PMC_TRAFFIC["kernels_sha256_16"] and args.bytes == PMC_TRAFFIC["bytes"]
+            and best == 0):
+        traffic = PMC_TRAFFIC["fetch"] + PMC_TRAFFIC["write"]
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -187,15 +328,17 @@ def main() -> int:
                                "16 KiB blocks, interleaved rANS, dependency levels <= 64",
                    "decompressed_bytes": N, "archive_bytes": len(a), "blocks": nb,
                    "levels": int(info.n_levels), "ratio": round(N / len(a), 4),
-                   "launch": "persistent, 3 workgroups/CU, per-block completion flags"},
+                   "launch": launch},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": None, "algorithmic_bytes_per_launch": algo,
+                     "traffic": traffic, "algorithmic_bytes_per_launch": algo,
                      "kernel": "k_decode", "avg_launch_ms": round(kern_ms, 4)},
         "cpu_baseline": cpu,
-        "baseline_per_level_launches_gbps": round(base_gbps, 2),
-        "range_window_gbps": round(range_gbps, 2),
+        "other_launch_mode_gbps": round(N / (float(np.mean(other)) / 1e3) / 1e9, 2) if other else None,
+        "range_window_gbps": round(range_gbps, 2) if range_gbps else None,
         "range_window": "whole file as consecutive 256 MiB lz_decode_range windows, bit-exact",
+        "read_access_us": read_lat,
+        "batched_lookups": batch_res,
         "encode_s": round(enc_s, 1),
     }
     print(json.dumps(line), flush=True)
