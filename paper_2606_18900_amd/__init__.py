@@ -4,3 +4,5 @@ include/lz.h; torch supplies device memory and streams)."""
 from ._lib import LzError, lib  # noqa: F401
 from .archive import Archive, encode, info  # noqa: F401
 from .batch import Batcher  # noqa: F401
+from .serve import Server  # noqa: F401,E402
+from .tune import tune  # noqa: F401,E402

@@ -19,7 +19,8 @@ class Batcher:
     until `results()` / `result(k)` read them."""
 
     def __init__(self, arc, n_max: int, out_cap: int, n_slots: int | None = None,
-                 use_graph: bool = True, stream: torch.cuda.Stream | None = None):
+                 use_graph: bool = True, stream: torch.cuda.Stream | None = None,
+                 scratch: torch.Tensor | None = None):
         self.arc = arc
         self.n_max = int(n_max)
         dev = arc.device
@@ -28,8 +29,12 @@ class Batcher:
         self.n = torch.zeros(1, dtype=torch.int32, device=dev)
         self.out = torch.empty(max(1, out_cap), dtype=torch.uint8, device=dev)
         self.offsets = torch.zeros(self.n_max + 1, dtype=torch.int64, device=dev)
-        self.scratch = torch.empty(arc.scratch_bytes(self.n_max, n_slots), dtype=torch.uint8,
-                                   device=dev)
+        # scratch may be shared by Batchers whose batches run on one stream
+        need = arc.scratch_bytes(self.n_max, n_slots)
+        if scratch is None:
+            scratch = torch.empty(need, dtype=torch.uint8, device=dev)
+        assert scratch.numel() >= need
+        self.scratch = scratch
         self.h_reqs = torch.zeros((self.n_max, 3), dtype=torch.int64).pin_memory()
         self.h_n = torch.zeros(1, dtype=torch.int32).pin_memory()
         self.count = 0
