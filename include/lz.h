@@ -87,9 +87,10 @@ typedef struct lz_request {
 
 /* Launch knobs (chosen by the autotuner; none of them changes a decoded byte). */
 typedef struct lz_tuning {
-  uint32_t sync_mode;   /* 0 = per-level launches, 1 = one persistent launch
-                           with per-block completion flags                   */
-  uint32_t wg_per_cu;   /* persistent grid = wg_per_cu * CUs (1..4)          */
+  uint32_t sync_mode;   /* 0 = per-level launches (lz_open's default), 1 = one
+                           persistent launch with per-block completion flags */
+  uint32_t wg_per_cu;   /* grid = wg_per_cu * CUs workgroups (a level launch
+                           takes at most its block count); 1..4, default 3   */
   uint32_t spin_limit;  /* watchdog: max polls of a dependency flag before the
                            kernel gives up with LZ_ECORRUPT (0 = default)     */
 } lz_tuning;

@@ -259,7 +259,7 @@ extern "C" int lz_open(const uint8_t* d_archive, uint64_t len, void* d_ws, uint6
   std::memcpy(h->level_count, count, sizeof(count));
   h->literal_bytes = lit_total;
   h->payload_bytes = prev_end;
-  h->tune.sync_mode = 1;
+  h->tune.sync_mode = 0;
   h->tune.wg_per_cu = 3;
   h->tune.spin_limit = 0;
   int dev = 0;
