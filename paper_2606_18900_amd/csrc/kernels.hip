@@ -32,7 +32,7 @@ constexpr uint32_t kMaxSeq = 1025;                // B/m + 1 for B = 16 KiB, m =
 constexpr uint32_t kLutLit = 1u << kMaxPLit;      // 4096 packed literal entries
 constexpr uint32_t kL = 1u << 16;                 // rANS state lower bound
 
-// All LDS is static (about 45 KB, three workgroups per CU): literal LUT,
+// All LDS is static (about 47.7 KB, three workgroups per CU): literal LUT,
 // output tile, small-stream cumulative tables, per-sequence tables.
 struct Smem {
   uint32_t lut[kLutLit];
@@ -43,6 +43,7 @@ struct Smem {
   uint32_t oflo[kMaxSeq];      // absolute source offsets, low 32 bits
   uint8_t ofhi[kMaxSeq + 3];   // bits 32..39
   uint16_t intl[kMaxSeq];      // matches whose source touches the block itself
+  uint16_t ring[kWaves][256];  // rANS words staged per wave (two 128-word slices)
   uint32_t scan[kWaves];
   uint32_t item, err, nint;
 };
@@ -133,15 +134,13 @@ __device__ __forceinline__ bool parse_stream(const uint8_t* pay, uint32_t plen, 
 // Decode the symbols of 64-lane group g of a rANS stream with one wave.
 // `body` is the record body in global memory (states, per-group word counts,
 // words).  `sym(u)` maps slot u to symbol | f << 8 | (u - c_s) << 20 and
-// `out(i, s)` consumes symbol i.  The group's 16-bit words are read through a
-// window of three 64-word slices held one word per lane; a lane needing word
-// idx (always inside the first two slices) takes it with a cross-lane shuffle,
-// and when 64 words have been consumed the window slides and the slice two
-// ahead is loaded, so loads run about five rounds ahead of use.
+// `out(i, s)` consumes symbol i.  The group's 16-bit words are staged through
+// the wave's LDS ring (two 128-word slices, the next slice loading into
+// registers meanwhile), so a lane needing word idx reads it from LDS.
 // True if every state ends at 2^16 and every word of the group was read.
 template <class Sym, class Out>
 __device__ bool rans_group(const uint8_t* body, const Stream& s, uint32_t g, uint32_t P,
-                           Sym&& sym, Out&& out) {
+                           uint16_t* ring, Sym&& sym, Out&& out) {
   const uint32_t lane = lane_id();
   const uint32_t K = s.K, n = s.n, G = (K + 63) >> 6;
   const uint32_t k = (g << 6) + lane;
@@ -152,41 +151,57 @@ __device__ bool rans_group(const uint8_t* body, const Stream& s, uint32_t g, uin
     if (q < g) woff += c;
     if (q == g) nwg = c;
   }
-  const uint16_t* W = reinterpret_cast<const uint16_t*>(body + 4 * K + 4 * G) + woff;
-  auto ldw = [&](uint32_t idx) -> uint32_t { return idx < nwg ? (uint32_t)W[idx] : 0u; };
+  // Word loads are unconditional: an index past the group's end reads the
+  // group's last word (or, for a group without words, the first state), so
+  // every load stays inside the record; a corrupt stream that consumes more
+  // words than the group holds fails the end check (pos == nwg).
+  const uint16_t* W = nwg ? reinterpret_cast<const uint16_t*>(body + 4 * K + 4 * G) + woff
+                          : reinterpret_cast<const uint16_t*>(body);
+  const uint32_t lastw = nwg ? nwg - 1 : 0;
+  auto ldw = [&](uint32_t idx) -> uint32_t { return (uint32_t)W[min(idx, lastw)]; };
   uint32_t x = lane_ok ? ld32(body + 4 * k) : kL;
   bool ok = x >= kL && woff + nwg <= s.nw;
-  uint32_t w0 = ldw(lane), w1 = ldw(64 + lane), w2 = ldw(128 + lane);
-  uint32_t pos = 0, base = 0;
-  const uint32_t rounds = (n + K - 1) / K;
+  // Ring of two 128-word slices: with s = pos / 128, slices s and s+1 are in
+  // the ring and slice s+2 is in flight in registers (pa, pb).
+  {
+    const uint32_t a0 = ldw(lane), a1 = ldw(64 + lane), a2 = ldw(128 + lane), a3 = ldw(192 + lane);
+    ring[lane] = (uint16_t)a0;
+    ring[64 + lane] = (uint16_t)a1;
+    ring[128 + lane] = (uint16_t)a2;
+    ring[192 + lane] = (uint16_t)a3;
+  }
+  uint32_t pa = ldw(256 + lane), pb = ldw(320 + lane);
+  uint32_t pos = 0;
+  const uint32_t rounds = (n + K - 1) / K, full = n / K;
   const uint32_t mask = (1u << P) - 1;
   uint32_t i = k;
-  for (uint32_t r = 0; r < rounds; r++, i += K) {
-    const bool act = lane_ok && i < n;
+  auto round = [&](bool act) {
     if (act) {
       const uint32_t e = sym(x & mask);
       x = __umul24((e >> 8) & 0xFFFu, x >> P) + (e >> 20);
       out(i, e & 0xFFu);
     }
+    i += K;
     const bool need = act && x < kL;
     const uint64_t bal = __ballot(need);
     if (bal) {
-      const uint32_t local = (pos - base) + mbcnt(bal);      // < 128
-      const uint32_t a0 = __shfl(w0, (int)(local & 63), 64);
-      const uint32_t a1 = __shfl(w1, (int)(local & 63), 64);
-      if (need) {
-        ok = ok && pos + mbcnt(bal) < nwg;
-        x = (x << 16) | (local < 64 ? a0 : a1);
-      }
+      if (need) x = (x << 16) | (uint32_t)ring[(pos + mbcnt(bal)) & 255];
+      const uint32_t s0 = pos >> 7;
       pos += (uint32_t)__popcll(bal);
-      if (pos - base >= 64) {
-        w0 = w1;
-        w1 = w2;
-        base += 64;
-        w2 = ldw(base + 128 + lane);
+      if ((pos >> 7) != s0) {          // entered slice s0+1: stage s0+2, fetch s0+3
+        __builtin_amdgcn_wave_barrier();   // after every lane's read of slice s0
+        uint16_t* d = ring + ((s0 & 1) << 7) + lane;
+        d[0] = (uint16_t)pa;
+        d[64] = (uint16_t)pb;
+        const uint32_t b3 = (s0 + 3) << 7;
+        pa = ldw(b3 + lane);
+        pb = ldw(b3 + 64 + lane);
       }
     }
-  }
+  };
+  // rounds in which every lane of the stream decodes, then the partial one
+  for (uint32_t r = 0; r < full; r++) round(lane_ok);
+  if (full < rounds) round(lane_ok && i < n);
   ok = ok && (!lane_ok || x == kL) && pos == nwg;
   return __ballot(!ok) == 0;
 }
@@ -278,7 +293,7 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
     };
     bool okw = true;
     if (s.mode == kModeRans) {
-      okw = rans_group(pay + s.body, s, 0, A.P[1 + wv],
+      okw = rans_group(pay + s.body, s, 0, A.P[1 + wv], S.ring[wv],
                        [&](uint32_t u) { return search_sym(cum, u); }, put);
     } else if (s.mode == kModeRaw) {
       const uint8_t* src = pay + s.body;
@@ -344,7 +359,7 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
     if (sl.mode == kModeRans) {
       const uint32_t G = (sl.K + 63) >> 6;
       for (uint32_t g = wv; g < G; g += kWaves)
-        if (!rans_group(pay + sl.body, sl, g, A.P[kLit], [&](uint32_t u) { return S.lut[u]; }, place)) bad = true;
+        if (!rans_group(pay + sl.body, sl, g, A.P[kLit], S.ring[wv], [&](uint32_t u) { return S.lut[u]; }, place)) bad = true;
     } else if (sl.mode == kModeRaw) {
       const uint8_t* src = pay + sl.body;
       for (uint32_t i = t; i < sl.n; i += kWG) place(i, src[i]);
@@ -462,8 +477,20 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
       const uint32_t d0 = S.lit[a], M = S.out[a];
       const int32_t s = (int32_t)(pk & 0xFFFFu) - 16384;
       const uint32_t d = (pk >> 16) & 0x7FFFu;
-      uint32_t r = lane % d;                // (c + lane) mod d, kept incrementally
-      const uint32_t r64 = 64u % d;
+      if (d >= M) {                         // no overlap with itself: a plain copy
+        for (uint32_t k = lane; k < M; k += 64) {
+          if (d0 + k < blen) {
+            const int32_t src = s + (int32_t)k;
+            const uint32_t v = src >= 0 ? (uint32_t)S.tile[(uint32_t)src & (kB - 1)]
+                                        : src_byte(A, sb + (int64_t)src, bad);
+            S.tile[d0 + k] = (uint8_t)v;
+          }
+        }
+        return;
+      }
+      // (c + lane) mod d, kept incrementally (a division only for d < 64)
+      uint32_t r = d >= 64 ? lane : lane % d;
+      const uint32_t r64 = d >= 64 ? 64u : 64u % d;
       for (uint32_t c = 0; c < M; c += 64) {
         const uint32_t k = c + lane;
         if (k < M && d0 + k < blen) {
