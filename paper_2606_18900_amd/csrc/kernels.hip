@@ -407,7 +407,7 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
   //     (binary search over the sorted destinations), packed into the
   //     sequence tables, which are no longer needed;
   // 4c: independent matches copied by all waves in parallel;
-  // 4d: dependent matches copied in order by wave 0.
+  // 4d: dependent matches copied in order by wave 0, one LDS round trip each.
   if (wv == 0) {
     uint32_t base = 0;
     for (uint32_t q0 = 0; q0 < ns; q0 += 64) {
@@ -508,13 +508,54 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
       if (!(S.oflo[a] & 0x80000000u)) copy_match(a);
     __syncthreads();
     // 4d: dependent matches in order, wave 0 (LDS operations of one wave are
-    // performed in order, so each copy sees the previous ones)
-    if (wv == 0)
-      for (uint32_t a = 0; a < cnt; a++)
-        if (S.oflo[a] & 0x80000000u) {
-          copy_match(a);
-          __builtin_amdgcn_wave_barrier();
+    // performed in order, so each copy sees the previous ones).  Their
+    // entries are first moved to the front of the tables (an order-keeping
+    // compaction, in place: 64 entries are read before any is written, and a
+    // write never passes the read position); then each copy's source load is
+    // issued together with the next entry's loads, so a dependent chain pays
+    // one LDS round trip per match.
+    if (wv == 0) {
+      uint32_t nd = 0;
+      for (uint32_t a0 = 0; a0 < cnt; a0 += 64) {
+        const uint32_t a = a0 + lane;
+        uint32_t pk = 0, e0 = 0, eM = 0;
+        if (a < cnt) {
+          pk = S.oflo[a];
+          e0 = S.lit[a];
+          eM = S.out[a];
         }
+        const bool dep = a < cnt && (pk & 0x80000000u);
+        const uint64_t m = __ballot(dep);
+        __builtin_amdgcn_wave_barrier();
+        if (dep) {
+          const uint32_t j = nd + mbcnt(m);
+          S.oflo[j] = pk;
+          S.lit[j] = (uint16_t)e0;
+          S.out[j] = (uint16_t)eM;
+        }
+        nd += (uint32_t)__popcll(m);
+        __builtin_amdgcn_wave_barrier();
+      }
+      uint32_t pk = nd ? S.oflo[0] : 0u, e0 = nd ? S.lit[0] : 0u, eM = nd ? S.out[0] : 0u;
+      for (uint32_t j = 0; j < nd; j++) {
+        const int32_t sj = (int32_t)(pk & 0xFFFFu) - 16384;
+        const uint32_t dj = (pk >> 16) & 0x7FFFu;
+        const bool simple = sj >= 0 && dj >= eM && eM <= 64;
+        uint32_t v = 0;
+        if (simple && lane < eM) v = S.tile[(uint32_t)sj + lane];
+        const uint32_t jn = j + 1 < nd ? j + 1 : j;
+        const uint32_t pkn = S.oflo[jn], e0n = S.lit[jn], eMn = S.out[jn];
+        if (simple) {
+          if (lane < eM && e0 + lane < blen) S.tile[e0 + lane] = (uint8_t)v;
+        } else {
+          copy_match(j);
+        }
+        __builtin_amdgcn_wave_barrier();
+        pk = pkn;
+        e0 = e0n;
+        eM = eMn;
+      }
+    }
     if (bad) S.err = 1;
   }
   __syncthreads();
