@@ -47,7 +47,7 @@ extern "C" {
 #define LZ_ECORRUPT (-7)  /* device-side decode check failed                  */
 #define LZ_EBUDGET  (-8)  /* serving admission refused (budget)               */
 
-/* Encoder parameters (container format v1).  The match search is global and
+/* Encoder parameters (container format v2).  The match search is global and
  * greedy with absolute source positions (Background section); blocks are
  * 2^block_log2 bytes (16 KB in the paper); levels are capped at max_level-1. */
 typedef struct lz_params {

@@ -3,7 +3,7 @@
  *
  * Written for reading, not speed: byte loops, full-size tables, no blocking,
  * no fusion.  Each section names the paper passage (or the reading of it) that
- * it follows.  Container format v1 is defined by the code below and by the
+ * it follows.  Container format v2 is defined by the code below and by the
  * design notes; nothing here is shared with the HIP library.
  */
 #include "oracle.h"
@@ -152,10 +152,21 @@ static void cumulative(const uint16_t* freq, uint32_t* cum) {
   for (int s = 0; s < 256; s++) cum[s + 1] = cum[s] + freq[s];
 }
 
-/* Encode symbols n-1 .. 0; symbol i goes to lane i mod K.  Before encoding s
- * a lane whose state is >= f_s * 2^(32-P) emits its low 16 bits.  Body:
- * u32 final state per lane, u32 word count per 64-lane group, then each
- * group's words in ascending symbol index. */
+/* Lane layout: lane k of K holds one run of consecutive symbols.  With
+ * R = n / K and e = n mod K, lane k holds len_k = R + (k < e) symbols starting
+ * at start_k = k R + min(k, e).  Decoding goes in rounds: in round r every lane
+ * with r < len_k decodes its symbol start_k + r; the decoder's slot of (r, k)
+ * is r K + k. */
+static uint32_t run_len(uint32_t k, uint32_t R, uint32_t e) { return R + (k < e ? 1u : 0u); }
+static uint64_t run_start(uint32_t k, uint32_t R, uint32_t e) {
+  return (uint64_t)k * R + (k < e ? k : e);
+}
+
+/* Encode in the reverse of the decoder's order (rounds from last to first,
+ * lanes from K-1 to 0).  Before encoding s a lane whose state is
+ * >= f_s * 2^(32-P) emits its low 16 bits.  Body: u32 final state per lane,
+ * u32 word count per 64-lane group, then each group's words in the decoder's
+ * slot order. */
 int orc_rans_encode(const uint8_t* sym, uint32_t n, const uint16_t* freq,
                     uint32_t P, uint32_t K, uint8_t** body, uint64_t* body_len,
                     uint32_t* n_words) {
@@ -165,24 +176,27 @@ int orc_rans_encode(const uint8_t* sym, uint32_t n, const uint16_t* freq,
   if (cum[256] != (1u << P)) return ORC_EINVAL;
   for (uint32_t i = 0; i < n; i++)
     if (!freq[sym[i]]) return ORC_EINVAL;
-  uint32_t G = (K + 63) / 64;
+  uint32_t G = (K + 63) / 64, R = n / K, e = n % K;
+  uint64_t slots = (uint64_t)((n + K - 1) / K) * K;
   uint64_t x[256];
   for (uint32_t k = 0; k < K; k++) x[k] = RANS_L;
-  int32_t* word = (int32_t*)malloc((n ? n : 1) * sizeof(int32_t));
+  int32_t* word = (int32_t*)malloc((slots ? slots : 1) * sizeof(int32_t));
   if (!word) return ORC_EINVAL;
-  for (uint32_t ii = n; ii-- > 0;) {
-    uint32_t k = ii % K, s = sym[ii], f = freq[s];
+  for (uint64_t o = slots; o-- > 0;) {
+    uint32_t r = (uint32_t)(o / K), k = (uint32_t)(o % K);
+    word[o] = -1;
+    if (r >= run_len(k, R, e)) continue;
+    uint32_t s = sym[run_start(k, R, e) + r], f = freq[s];
     uint64_t xmax = (uint64_t)f << (32 - P);
-    word[ii] = -1;
     if (x[k] >= xmax) {
-      word[ii] = (int32_t)(x[k] & 0xFFFF);
+      word[o] = (int32_t)(x[k] & 0xFFFF);
       x[k] >>= 16;
     }
     x[k] = (x[k] / f) * (1ull << P) + (x[k] % f) + cum[s];
   }
   uint32_t gw[4] = {0, 0, 0, 0}, nw = 0;
-  for (uint32_t i = 0; i < n; i++)
-    if (word[i] >= 0) { gw[(i % K) / 64]++; nw++; }
+  for (uint64_t o = 0; o < slots; o++)
+    if (word[o] >= 0) { gw[(o % K) / 64]++; nw++; }
   uint64_t len = 4ull * K + 4ull * G + 2ull * nw;
   uint8_t* out = (uint8_t*)malloc(len ? len : 1);
   if (!out) { free(word); return ORC_EINVAL; }
@@ -190,8 +204,8 @@ int orc_rans_encode(const uint8_t* sym, uint32_t n, const uint16_t* freq,
   for (uint32_t k = 0; k < K; k++, q += 4) put32(q, x[k]);
   for (uint32_t g = 0; g < G; g++, q += 4) put32(q, gw[g]);
   for (uint32_t g = 0; g < G; g++)
-    for (uint32_t i = 0; i < n; i++)
-      if (word[i] >= 0 && (i % K) / 64 == g) { put16(q, (uint32_t)word[i]); q += 2; }
+    for (uint64_t o = 0; o < slots; o++)
+      if (word[o] >= 0 && (o % K) / 64 == g) { put16(q, (uint32_t)word[o]); q += 2; }
   free(word);
   *body = out;
   *body_len = len;
@@ -232,20 +246,18 @@ int orc_rans_decode(const uint8_t* body, uint64_t body_len, uint32_t n,
   }
   if (tot != n_words) { free(slot_sym); return ORC_ECORRUPT; }
   const uint8_t* W = body + 4 * K + 4 * G;
-  uint32_t rounds = (n + K - 1) / K;
+  uint32_t rounds = (n + K - 1) / K, R = n / K, e = n % K;
   int rc = ORC_OK;
   for (uint32_t r = 0; r < rounds && rc == ORC_OK; r++) {
     for (uint32_t k = 0; k < K; k++) {
-      uint64_t i = (uint64_t)r * K + k;
-      if (i >= n) break;
+      if (r >= run_len(k, R, e)) continue;
       uint32_t slot = (uint32_t)(x[k] & (M - 1));
       uint32_t s = slot_sym[slot];
       x[k] = (uint64_t)freq[s] * (x[k] >> P) + slot - cum[s];
-      out[i] = (uint8_t)s;
+      out[run_start(k, R, e) + r] = (uint8_t)s;
     }
     for (uint32_t k = 0; k < K; k++) {
-      uint64_t i = (uint64_t)r * K + k;
-      if (i >= n) break;
+      if (r >= run_len(k, R, e)) continue;
       if (x[k] < RANS_L) {
         uint32_t g = k / 64;
         if (gpos[g] >= gw[g]) { rc = ORC_ECORRUPT; break; }
@@ -698,7 +710,7 @@ int orc_encode(const uint8_t* x, uint64_t n, const orc_params* pr,
     if (!rc) {
       uint8_t* h = A.p;
       memcpy(h, "LZAB", 4);
-      put16(h + 4, 1);
+      put16(h + 4, 2);
       put16(h + 6, (pr->kind == 1 ? 1u : 0u) | (pr->level_penalty << 8));
       h[8] = (uint8_t)pr->block_log2;
       h[9] = (uint8_t)pr->max_level;
@@ -756,7 +768,7 @@ static int in_bounds(uint64_t off, uint64_t sz, uint64_t len) {
 static int open_view(const uint8_t* a, uint64_t len, view_t* v) {
   memset(v, 0, sizeof(*v));
   if (!a || len < HDR_SIZE) return ORC_EFORMAT;
-  if (memcmp(a, "LZAB", 4) || get16(a + 4) != 1) return ORC_EFORMAT;
+  if (memcmp(a, "LZAB", 4) || get16(a + 4) != 2) return ORC_EFORMAT;
   if (get64(a + 120) != orc_fnv1a64(a, 120, FNV_BASIS)) return ORC_EFORMAT;
   v->a = a;
   v->len = len;

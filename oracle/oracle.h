@@ -16,7 +16,7 @@
  *   - the read -> record-start index (Read-Level Index section: 8 bytes/read);
  *   - FNV-1a-64 block hashes (Experimental Setup: FNV on device paths).
  * Every step the paper leaves open follows the readings listed in the design
- * notes (container format v1); each function below names its step.
+ * notes (container format v2); each function below names its step.
  */
 #ifndef LZ_ORACLE_H
 #define LZ_ORACLE_H

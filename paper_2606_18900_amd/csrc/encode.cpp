@@ -1,4 +1,4 @@
-// Host encoder (lz_encode) for container format v1.
+// Host encoder (lz_encode) for container format v2.
 //
 // Global greedy match search whose matches carry absolute source positions in
 // the decompressed output (paper, Background section), fixed-size blocks
@@ -321,42 +321,48 @@ struct Table {
   uint32_t P;
 };
 
-// Encode sym[0..n) with K interleaved lanes (symbol i -> lane i mod K), from
-// the last symbol to the first; emits the record body into `body`.
+// Encode sym[0..n) with K lanes.  Lane k owns the run of n/K consecutive
+// symbols (one more for the first n mod K lanes) that the decoder takes one per
+// round; decode slot o = r*K + k is round r of lane k.  The encoder walks the
+// slots backwards and stores each group's words in slot order.
 void rans_body(const uint8_t* sym, uint32_t n, const Table& t, uint32_t K,
                std::vector<uint8_t>& body, uint32_t& n_words) {
-  const uint32_t G = (K + 63) / 64;
+  const uint32_t G = (K + 63) / 64, R = n / K, e = n % K;
+  const uint64_t slots = (uint64_t)((n + K - 1) / K) * K;
   uint32_t x[256];
-  for (uint32_t k = 0; k < K; k++) x[k] = 1u << 16;
-  std::vector<uint16_t> w(n);
-  std::vector<uint8_t> has(n, 0);
-  for (uint32_t i = n; i-- > 0;) {
-    uint32_t k = i % K, s = sym[i], f = t.f[s];
+  uint64_t start[257];
+  for (uint32_t k = 0; k < K; k++) {
+    x[k] = 1u << 16;
+    start[k] = (uint64_t)k * R + std::min(k, e);
+  }
+  std::vector<uint16_t> w(slots);
+  std::vector<uint8_t> has(slots, 0);
+  for (uint64_t o = slots; o-- > 0;) {
+    const uint32_t r = (uint32_t)(o / K), k = (uint32_t)(o % K);
+    if (r >= R + (k < e ? 1u : 0u)) continue;
+    const uint32_t s = sym[start[k] + r], f = t.f[s];
     uint64_t xm = (uint64_t)f << (32 - t.P);
     uint64_t v = x[k];
     if (v >= xm) {
-      w[i] = (uint16_t)(v & 0xFFFF);
-      has[i] = 1;
+      w[o] = (uint16_t)(v & 0xFFFF);
+      has[o] = 1;
       v >>= 16;
     }
     x[k] = (uint32_t)((v / f) * (1ull << t.P) + (v % f) + t.c[s]);
   }
   uint32_t gw[4] = {0, 0, 0, 0}, nw = 0;
-  for (uint32_t i = 0; i < n; i++)
-    if (has[i]) { gw[(i % K) >> 6]++; nw++; }
+  for (uint64_t o = 0; o < slots; o++)
+    if (has[o]) { gw[(o % K) >> 6]++; nw++; }
   body.resize(4ull * K + 4ull * G + 2ull * nw);
-  uint8_t* o = body.data();
-  for (uint32_t k = 0; k < K; k++, o += 4) std::memcpy(o, &x[k], 4);
-  for (uint32_t g = 0; g < G; g++, o += 4) std::memcpy(o, &gw[g], 4);
-  // words of group g in ascending symbol index: lanes 64g..64g+63 of each round
+  uint8_t* op = body.data();
+  for (uint32_t k = 0; k < K; k++, op += 4) std::memcpy(op, &x[k], 4);
+  for (uint32_t g = 0; g < G; g++, op += 4) std::memcpy(op, &gw[g], 4);
+  // words of group g in slot order: lanes 64g..64g+63 of each round
   for (uint32_t g = 0; g < G; g++) {
-    uint32_t k0 = 64 * g, k1 = std::min(K, k0 + 64);
-    for (uint32_t r = 0; (uint64_t)r * K < n; r++)
-      for (uint32_t k = k0; k < k1; k++) {
-        uint64_t i = (uint64_t)r * K + k;
-        if (i >= n) break;
-        if (has[i]) { std::memcpy(o, &w[i], 2); o += 2; }
-      }
+    const uint32_t k0 = 64 * g, k1 = std::min(K, k0 + 64);
+    for (uint64_t r0 = 0; r0 < slots; r0 += K)
+      for (uint32_t k = k0; k < k1; k++)
+        if (has[r0 + k]) { std::memcpy(op, &w[r0 + k], 2); op += 2; }
   }
   n_words = nw;
 }
@@ -589,7 +595,7 @@ extern "C" int lz_encode(const uint8_t* x, uint64_t n, const lz_params* pp, uint
   // header
   uint8_t* h = A;
   std::memcpy(h, "LZAB", 4);
-  uint16_t ver = 1, flags = (uint16_t)((pr.kind == 1 ? 1u : 0u) | (pr.level_penalty << 8));
+  uint16_t ver = 2, flags = (uint16_t)((pr.kind == 1 ? 1u : 0u) | (pr.level_penalty << 8));
   std::memcpy(h + 4, &ver, 2);
   std::memcpy(h + 6, &flags, 2);
   h[8] = (uint8_t)bl;

@@ -1,4 +1,4 @@
-// Device decoder for container format v1 on gfx950 (CDNA4, wave64).
+// Device decoder for container format v2 on gfx950 (CDNA4, wave64).
 //
 // One workgroup of 256 threads (4 waves) decodes one block at a time:
 //   1. waves 0..2 decode the command (CMD), match-length (MLEN) and offset
@@ -172,16 +172,19 @@ __device__ bool rans_group(const uint8_t* body, const Stream& s, uint32_t g, uin
   }
   uint32_t pa = ldw(256 + lane), pb = ldw(320 + lane);
   uint32_t pos = 0;
-  const uint32_t rounds = (n + K - 1) / K, full = n / K;
+  // lane k decodes the run of consecutive symbols starting at
+  // k*full + min(k, extra): full = n / K symbols, one more for the first
+  // extra = n mod K lanes
+  const uint32_t full = n / K, extra = n - full * K;
   const uint32_t mask = (1u << P) - 1;
-  uint32_t i = k;
+  uint32_t i = k * full + min(k, extra);
   auto round = [&](bool act) {
     if (act) {
       const uint32_t e = sym(x & mask);
       x = __umul24((e >> 8) & 0xFFFu, x >> P) + (e >> 20);
       out(i, e & 0xFFu);
     }
-    i += K;
+    i += 1;
     const bool need = act && x < kL;
     const uint64_t bal = __ballot(need);
     if (bal) {
@@ -201,7 +204,7 @@ __device__ bool rans_group(const uint8_t* body, const Stream& s, uint32_t g, uin
   };
   // rounds in which every lane of the stream decodes, then the partial one
   for (uint32_t r = 0; r < full; r++) round(lane_ok);
-  if (full < rounds) round(lane_ok && i < n);
+  if (extra) round(lane_ok && k < extra);
   ok = ok && (!lane_ok || x == kL) && pos == nwg;
   return __ballot(!ok) == 0;
 }
@@ -345,8 +348,19 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
   // ---- stage 3: literals straight to their tile positions; external matches
   {
     bool bad = false;
-    uint32_t j = 0;                            // per-lane sequence cursor
-    uint32_t nxt = S.lit[1], dlt = S.out[0] - S.lit[0];
+    // per-lane sequence cursor: literal i belongs to sequence j, the last one
+    // with lit[j] <= i; its output position is i + (out[j] - lit[j])
+    uint32_t j = 0, nxt = S.lit[1], dlt = S.out[0] - S.lit[0];
+    auto seek = [&](uint32_t i) {              // binary search over lit[0..ns-1]
+      uint32_t lo = 0, hi = ns ? ns - 1 : 0;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (S.lit[mid] <= i) lo = mid; else hi = mid - 1;
+      }
+      j = lo;
+      nxt = S.lit[j + 1];
+      dlt = (uint32_t)S.out[j] - (uint32_t)S.lit[j];
+    };
     auto place = [&](uint32_t i, uint32_t v) {
       while (i >= nxt && j + 1 < ns) {
         j++;
@@ -357,9 +371,12 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
       if (a < blen) S.tile[a] = (uint8_t)v;
     };
     if (sl.mode == kModeRans) {
-      const uint32_t G = (sl.K + 63) >> 6;
-      for (uint32_t g = wv; g < G; g += kWaves)
+      const uint32_t G = (sl.K + 63) >> 6, R = sl.n / sl.K, e = sl.n - R * sl.K;
+      for (uint32_t g = wv; g < G; g += kWaves) {
+        const uint32_t k = (g << 6) + lane;   // this lane's run starts at k*R + min(k, e)
+        seek(min(k * R + min(k, e), sl.n - 1));
         if (!rans_group(pay + sl.body, sl, g, A.P[kLit], S.ring[wv], [&](uint32_t u) { return S.lut[u]; }, place)) bad = true;
+      }
     } else if (sl.mode == kModeRaw) {
       const uint8_t* src = pay + sl.body;
       for (uint32_t i = t; i < sl.n; i += kWG) place(i, src[i]);

@@ -1,5 +1,5 @@
 // Internal definitions shared by the library's host and device sources:
-// container format v1 layout constants, the handle, and error reporting.
+// container format v2 layout constants, the handle, and error reporting.
 #pragma once
 #include <cstdint>
 

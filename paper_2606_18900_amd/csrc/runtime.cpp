@@ -58,7 +58,7 @@ bool fits(uint64_t off, uint64_t sz, uint64_t len) { return off <= len && sz <= 
 // n_blocks = ceil(N / B), canonical offset width, section order).
 int parse_header(const uint8_t* a, uint64_t len, ArchiveView& v, uint64_t& total) {
   if (len < kHeaderSize) return lz_fail(LZ_EFORMAT, "archive shorter than its header");
-  if (std::memcmp(a, "LZAB", 4) || rd16(a + 4) != 1) return lz_fail(LZ_EFORMAT, "bad magic or version");
+  if (std::memcmp(a, "LZAB", 4) || rd16(a + 4) != 2) return lz_fail(LZ_EFORMAT, "bad magic or version");
   if (rd64(a + 120) != fnv1a(a, 120, kFnvBasis)) return lz_fail(LZ_EFORMAT, "header checksum mismatch");
   v = ArchiveView{};
   const uint32_t flags = rd16(a + 6);

@@ -80,23 +80,49 @@ def _cum(freq):
     return c
 
 
+def lane_runs(n: int, K: int):
+    """Each lane's run of consecutive symbols: the n symbols are cut into K
+    runs, the first n mod K of them one symbol longer.  Returns a list of
+    (start, length) per lane."""
+    runs, start = [], 0
+    for k in range(K):
+        ln = n // K + (1 if k < n % K else 0)
+        runs.append((start, ln))
+        start += ln
+    assert start == n
+    return runs
+
+
+def decode_order(n: int, K: int):
+    """(round, lane, symbol index) in the decoder's order: round by round, lanes
+    ascending, a lane taking part while its run lasts."""
+    runs = lane_runs(n, K)
+    order = []
+    for r in range(max((ln for _, ln in runs), default=0)):
+        for k, (st, ln) in enumerate(runs):
+            if r < ln:
+                order.append((r, k, st + r))
+    return order
+
+
 def rans_encode(sym: bytes, freq, P: int, K: int):
     """Return (states, group_words, words_by_group) — states are the encoder's
     final states, i.e. the decoder's initial states."""
     L = 1 << 16
     c = _cum(freq)
     x = [L] * K
+    order = decode_order(len(sym), K)
     emitted = {}
-    for i in range(len(sym) - 1, -1, -1):
-        k = i % K
+    for t in range(len(order) - 1, -1, -1):
+        _, k, i = order[t]
         s = sym[i]
         f = freq[s]
         if x[k] >= f << (32 - P):
-            emitted[i] = x[k] & 0xFFFF
+            emitted[t] = x[k] & 0xFFFF
             x[k] >>= 16
         x[k] = (x[k] // f) * (1 << P) + (x[k] % f) + c[s]
     G = (K + 63) // 64
-    groups = [[emitted[i] for i in sorted(emitted) if (i % K) // 64 == g] for g in range(G)]
+    groups = [[emitted[t] for t in sorted(emitted) if order[t][1] // 64 == g] for g in range(G)]
     return x, groups
 
 
@@ -107,14 +133,17 @@ def rans_decode(states, groups, n: int, freq, P: int, K: int) -> bytes:
     x = list(states)
     pos = [0] * len(groups)
     out = bytearray(n)
-    for r in range((n + K - 1) // K):
-        lanes = [k for k in range(K) if r * K + k < n]
-        for k in lanes:
+    order = decode_order(n, K)
+    rounds = {}
+    for r, k, i in order:
+        rounds.setdefault(r, []).append((k, i))
+    for r in sorted(rounds):
+        for k, i in rounds[r]:
             slot = x[k] % M
             s = next(t for t in range(256) if c[t] <= slot < c[t + 1])
             x[k] = freq[s] * (x[k] >> P) + slot - c[s]
-            out[r * K + k] = s
-        for k in lanes:
+            out[i] = s
+        for k, _ in rounds[r]:
             if x[k] < L:
                 g = k // 64
                 x[k] = (x[k] << 16) | groups[g][pos[g]]

@@ -66,6 +66,39 @@ def test_lanes_rule(orc):
     assert orc.rans_lanes(4100, 64, 4) == 64
 
 
+def test_lane_runs_hand_example():
+    # 5 symbols over 2 lanes: lane 0 holds symbols 0..2, lane 1 symbols 3..4;
+    # the decoder takes them round by round, lanes ascending
+    assert brute.lane_runs(5, 2) == [(0, 3), (3, 2)]
+    assert brute.decode_order(5, 2) == [(0, 0, 0), (0, 1, 3), (1, 0, 1), (1, 1, 4), (2, 0, 2)]
+    # fewer symbols than lanes: the tail lanes hold nothing
+    assert brute.lane_runs(2, 4) == [(0, 1), (1, 1), (2, 0), (2, 0)]
+
+
+def test_single_lane_is_plain_rans(orc):
+    """With one lane the body is the textbook rANS coder: a single state,
+    words in the order the decoder reads them (Duda 2013)."""
+    sym = bytes([3, 1, 4, 1, 5, 9, 2, 6, 5, 3, 5] * 20)
+    freq = _freq_for(orc, sym, 8)
+    rc, body, nw = orc.rans_encode(sym, freq, 8, 1)
+    assert rc == 0
+    c = [0]
+    for v in freq:
+        c.append(c[-1] + int(v))
+    x = 1 << 16
+    words = []
+    for s in reversed(sym):
+        f = int(freq[s])
+        if x >= f << 24:
+            words.append(x & 0xFFFF)
+            x >>= 16
+        x = (x // f) * 256 + x % f + c[s]
+    words.reverse()
+    ref = x.to_bytes(4, "little") + len(words).to_bytes(4, "little")
+    ref += b"".join(w.to_bytes(2, "little") for w in words)
+    assert body == ref and nw == len(words)
+
+
 def _streams():
     rng = np.random.default_rng(11)
     out = []
