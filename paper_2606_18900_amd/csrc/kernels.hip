@@ -32,7 +32,7 @@ constexpr uint32_t kMaxSeq = 1025;                // B/m + 1 for B = 16 KiB, m =
 constexpr uint32_t kLutLit = 1u << kMaxPLit;      // 4096 packed literal entries
 constexpr uint32_t kL = 1u << 16;                 // rANS state lower bound
 
-// All LDS is static (about 47.7 KB, three workgroups per CU): literal LUT,
+// All LDS is static (about 51.8 KB, three workgroups per CU): literal LUT,
 // output tile, small-stream cumulative tables, per-sequence tables.
 struct Smem {
   uint32_t lut[kLutLit];
@@ -44,6 +44,7 @@ struct Smem {
   uint8_t ofhi[kMaxSeq + 3];   // bits 32..39
   uint16_t intl[kMaxSeq];      // matches whose source touches the block itself
   uint16_t ring[kWaves][256];  // rANS words staged per wave (two 128-word slices)
+  uint32_t ringe[kWaves][256]; // literal stream: table entry of each staged word's slot
   uint32_t scan[kWaves];
   uint32_t item, err, nint;
 };
@@ -209,6 +210,94 @@ __device__ bool rans_group(const uint8_t* body, const Stream& s, uint32_t g, uin
   return __ballot(!ok) == 0;
 }
 
+// The literal stream's group decode: the same symbols, words and checks as
+// rans_group, with the next table lookup of a renormalising lane folded into
+// its word read.  After x = (x << 16) | w the next slot is w mod 2^P (P <= 12),
+// so every word staged into the ring carries the table entry of that slot.  A
+// round then makes one LDS round trip: lanes that take a word read the word
+// and its entry, the others look up their new slot, in the same wait.
+// `out(i, s, act)` is called by every lane of the wave each round; only lanes
+// with act set hold symbol i.
+template <class Out>
+__device__ bool rans_lit(const uint8_t* body, const Stream& s, uint32_t g, uint32_t P,
+                         const uint32_t* lut, uint16_t* ring, uint32_t* ringe, Out&& out) {
+  const uint32_t lane = lane_id();
+  const uint32_t K = s.K, n = s.n, G = (K + 63) >> 6;
+  const uint32_t k = (g << 6) + lane;
+  const bool lane_ok = k < K;
+  uint32_t woff = 0, nwg = 0;
+  for (uint32_t q = 0; q < G; q++) {
+    const uint32_t c = ld32(body + 4 * K + 4 * q);
+    if (q < g) woff += c;
+    if (q == g) nwg = c;
+  }
+  // unconditional word loads, clamped into the group as in rans_group
+  const uint16_t* W = nwg ? reinterpret_cast<const uint16_t*>(body + 4 * K + 4 * G) + woff
+                          : reinterpret_cast<const uint16_t*>(body);
+  const uint32_t lastw = nwg ? nwg - 1 : 0;
+  auto ldw = [&](uint32_t idx) -> uint32_t { return (uint32_t)W[min(idx, lastw)]; };
+  const uint32_t mask = (1u << P) - 1;
+  uint32_t x = lane_ok ? ld32(body + 4 * k) : kL;
+  bool ok = x >= kL && woff + nwg <= s.nw;
+  // ring of two 128-word slices as in rans_group; slice s+2 waits in pa, pb
+  {
+    uint32_t a[4];
+#pragma unroll
+    for (uint32_t q = 0; q < 4; q++) a[q] = ldw(64 * q + lane);
+#pragma unroll
+    for (uint32_t q = 0; q < 4; q++) {
+      ring[64 * q + lane] = (uint16_t)a[q];
+      ringe[64 * q + lane] = lut[a[q] & mask];
+    }
+  }
+  uint32_t pa = ldw(256 + lane), pb = ldw(320 + lane);
+  uint32_t e = lut[x & mask];
+  uint32_t pos = 0;
+  const uint32_t full = n / K, extra = n - full * K;
+  uint32_t i = k * full + min(k, extra);
+  // One round.  Both reads are issued by every lane (a lane without a word
+  // reads a word it ignores; a lane with one takes its entry from the ring
+  // instead of the table), then the symbol's tile store, so the next round
+  // waits for the reads alone.
+  auto round = [&](bool act) {
+    const uint32_t xd = __umul24((e >> 8) & 0xFFFu, x >> P) + (e >> 20);
+    const uint32_t sym = e & 0xFFu;
+    if (act) x = xd;
+    const bool need = act && x < kL;
+    const uint64_t bal = __ballot(need);
+    const uint32_t q = (pos + mbcnt(bal)) & 255;
+    const uint32_t w = ring[q];
+    e = need ? ringe[q] : lut[x & mask];
+    out(i, sym, act);
+    i += 1;
+    x = need ? (x << 16) | w : x;
+    if (bal) {
+      const uint32_t s0 = pos >> 7;
+      pos += (uint32_t)__popcll(bal);
+      if ((pos >> 7) != s0) {          // entered slice s0+1: stage s0+2, fetch s0+3
+        __builtin_amdgcn_wave_barrier();   // after every lane's read of slice s0
+        const uint32_t ea = lut[pa & mask], eb = lut[pb & mask];
+        const uint32_t d = ((s0 & 1) << 7) + lane;
+        ring[d] = (uint16_t)pa;
+        ring[d + 64] = (uint16_t)pb;
+        ringe[d] = ea;
+        ringe[d + 64] = eb;
+        const uint32_t b3 = (s0 + 3) << 7;
+        pa = ldw(b3 + lane);
+        pb = ldw(b3 + 64 + lane);
+      }
+    }
+  };
+  if ((g << 6) + 64 <= K) {
+    for (uint32_t r = 0; r < full; r++) round(true);   // every lane of the group decodes
+  } else {
+    for (uint32_t r = 0; r < full; r++) round(lane_ok);
+  }
+  if (extra) round(lane_ok && k < extra);
+  ok = ok && (!lane_ok || x == kL) && pos == nwg;
+  return __ballot(!ok) == 0;
+}
+
 // Source byte at absolute position a (an earlier block): direct mode reads the
 // whole-file output; request mode goes through the per-block address table.
 __device__ __forceinline__ uint32_t src_byte(const DevArgs& A, uint64_t a, bool& bad) {
@@ -361,27 +450,34 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
       nxt = S.lit[j + 1];
       dlt = (uint32_t)S.out[j] - (uint32_t)S.lit[j];
     };
-    auto place = [&](uint32_t i, uint32_t v) {
-      while (i >= nxt && j + 1 < ns) {
-        j++;
-        nxt = S.lit[j + 1];
-        dlt = (uint32_t)S.out[j] - (uint32_t)S.lit[j];
+    // called by every lane of the wave; lanes with act false store nothing
+    auto place = [&](uint32_t i, uint32_t v, bool act) {
+      if (__ballot(act && i >= nxt && j + 1 < ns)) {   // some lane entered a later sequence
+        while (act && i >= nxt && j + 1 < ns) {
+          j++;
+          nxt = S.lit[j + 1];
+          dlt = (uint32_t)S.out[j] - (uint32_t)S.lit[j];
+        }
       }
-      const uint32_t a = i + dlt;
-      if (a < blen) S.tile[a] = (uint8_t)v;
+      // i < lit[j+1] and the scans checked in stage 2 put i + dlt below
+      // out[j+1] <= blen; the mask only keeps the store inside the tile
+      if (act) S.tile[(i + dlt) & (kB - 1)] = (uint8_t)v;
     };
     if (sl.mode == kModeRans) {
       const uint32_t G = (sl.K + 63) >> 6, R = sl.n / sl.K, e = sl.n - R * sl.K;
       for (uint32_t g = wv; g < G; g += kWaves) {
         const uint32_t k = (g << 6) + lane;   // this lane's run starts at k*R + min(k, e)
         seek(min(k * R + min(k, e), sl.n - 1));
-        if (!rans_group(pay + sl.body, sl, g, A.P[kLit], S.ring[wv], [&](uint32_t u) { return S.lut[u]; }, place)) bad = true;
+        if (!rans_lit(pay + sl.body, sl, g, A.P[kLit], S.lut, S.ring[wv], S.ringe[wv], place)) bad = true;
       }
     } else if (sl.mode == kModeRaw) {
       const uint8_t* src = pay + sl.body;
-      for (uint32_t i = t; i < sl.n; i += kWG) place(i, src[i]);
+      for (uint32_t i0 = 0; i0 < sl.n; i0 += kWG) {
+        const uint32_t i = i0 + t;
+        place(i, i < sl.n ? src[i] : 0u, i < sl.n);
+      }
     } else if (sl.mode == kModeConst) {
-      for (uint32_t i = t; i < sl.n; i += kWG) place(i, sl.csym);
+      for (uint32_t i0 = 0; i0 < sl.n; i0 += kWG) place(i0 + t, sl.csym, i0 + t < sl.n);
     }
     // matches with a source wholly in earlier blocks: copy now, in parallel
     for (uint32_t q = wv; q < ns; q += kWaves) {
