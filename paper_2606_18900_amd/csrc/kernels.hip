@@ -38,11 +38,13 @@ struct Smem {
   uint32_t lut[kLutLit];
   alignas(16) uint8_t tile[kB];
   uint16_t cum[3][257];        // CMD, MLEN, OFF cumulative frequencies
+  uint8_t bkt[3][256];         // per stream: symbol owning the first slot of each bucket
   uint16_t lit[kMaxSeq + 1];   // LL values, then exclusive scan of LL ([ns] = n_lit)
   uint16_t out[kMaxSeq + 1];   // ML values, then exclusive scan of LL+ML ([ns] = block length)
   uint32_t oflo[kMaxSeq];      // absolute source offsets, low 32 bits
   uint8_t ofhi[kMaxSeq + 3];   // bits 32..39
   uint16_t intl[kMaxSeq];      // matches whose source touches the block itself
+  uint8_t plist[64];           // dependent matches of one pass (chunk-relative)
   uint16_t ring[kWaves][256];  // rANS words staged per wave (two 128-word slices)
   uint32_t ringe[kWaves][256]; // literal stream: table entry of each staged word's slot
   uint32_t scan[kWaves];
@@ -335,8 +337,22 @@ __device__ __forceinline__ uint32_t search_sym(const uint16_t* cum, uint32_t u) 
 #pragma unroll
   for (uint32_t step = 128; step; step >>= 1)
     if (cum[lo + step] <= u) lo += step;
-  const uint32_t c = cum[lo], f = cum[lo + 1] - c;
-  return lo | ((f & 0xFFFu) << 8) | ((u - c) << 20);
+  return lo;
+}
+
+// Symbol owning slot u of a short stream, packed like a literal LUT entry.
+// The bucket of u (2^bs slots) names the owner of its first slot; the owner
+// of u is that symbol or one of the at most 2^bs - 1 symbols after it.
+__device__ __forceinline__ uint32_t bucket_sym(const uint16_t* cum, const uint8_t* bkt,
+                                               uint32_t bs, uint32_t u) {
+  uint32_t s = bkt[u >> bs];
+  uint32_t c0 = cum[s], c1 = cum[s + 1];
+  while (c1 <= u && s < 255) {
+    s++;
+    c0 = c1;
+    c1 = cum[s + 1];
+  }
+  return s | (((c1 - c0) & 0xFFFu) << 8) | ((u - c0) << 20);
 }
 
 // Decode block b into the LDS tile and store it.  Every loop below is bounded
@@ -371,6 +387,7 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
   if (wv < 3) {
     const Stream& s = wv == 0 ? sc : (wv == 1 ? sm : so);
     const uint16_t* cum = S.cum[wv];
+    const uint32_t bs = A.P[1 + wv] > 8 ? A.P[1 + wv] - 8 : 0u;
     uint8_t* dst8 = wv == 0 ? reinterpret_cast<uint8_t*>(S.lit) : reinterpret_cast<uint8_t*>(S.out);
     auto put = [&](uint32_t i, uint32_t v) {
       uint32_t plane = 0, idx = i;
@@ -386,7 +403,7 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
     bool okw = true;
     if (s.mode == kModeRans) {
       okw = rans_group(pay + s.body, s, 0, A.P[1 + wv], S.ring[wv],
-                       [&](uint32_t u) { return search_sym(cum, u); }, put);
+                       [&](uint32_t u) { return bucket_sym(cum, S.bkt[wv], bs, u); }, put);
     } else if (s.mode == kModeRaw) {
       const uint8_t* src = pay + s.body;
       for (uint32_t i = lane; i < s.n; i += 64) put(i, src[i]);
@@ -419,6 +436,8 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
       const uint64_t of = (uint64_t)S.oflo[j] | ((uint64_t)S.ofhi[j] << 32);
       if (ml[q] == 0) bad |= (j != ns - 1) || of != 0;
       else bad |= ml[q] < A.m || of >= sb + po + ll[q];
+      // matches with a source wholly in earlier blocks, listed in any order
+      if (ml[q] && of + ml[q] <= sb) S.intl[atomicAdd(&S.nint, 1u)] = (uint16_t)j;
       pl += ll[q];
       po += ll[q] + ml[q];
     }
@@ -479,24 +498,28 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
     } else if (sl.mode == kModeConst) {
       for (uint32_t i0 = 0; i0 < sl.n; i0 += kWG) place(i0 + t, sl.csym, i0 + t < sl.n);
     }
-    // matches with a source wholly in earlier blocks: copy now, in parallel
-    for (uint32_t q = wv; q < ns; q += kWaves) {
-      const uint32_t L = (uint32_t)S.lit[q + 1] - S.lit[q];
-      const uint32_t M = (uint32_t)S.out[q + 1] - S.out[q] - L;
-      if (!M) continue;
-      const uint64_t of = (uint64_t)S.oflo[q] | ((uint64_t)S.ofhi[q] << 32);
-      const uint32_t d0 = S.out[q] + L;
-      if (of + M <= sb) {
-        for (uint32_t k0 = 0; k0 < M; k0 += 256) {   // four independent loads in flight
-          uint32_t v[4];
+    // matches with a source wholly in earlier blocks (listed in stage 2):
+    // eight per wave at a time, one per 8-lane slot, each lane every eighth
+    // byte, all loads in flight before the stores
+    {
+      const uint32_t nx = min(S.nint, ns), slot = lane >> 3, sub = lane & 7;
+      for (uint32_t g0 = 8 * wv; g0 < nx; g0 += 8 * kWaves) {
+        const uint32_t e = g0 + slot;
+        const uint32_t q = e < nx ? min((uint32_t)S.intl[e], ns - 1) : 0u;
+        const uint32_t L = (uint32_t)S.lit[q + 1] - S.lit[q];
+        const uint32_t M = e < nx ? (uint32_t)S.out[q + 1] - S.out[q] - L : 0u;
+        const uint64_t of = (uint64_t)S.oflo[q] | ((uint64_t)S.ofhi[q] << 32);
+        const uint32_t d0 = S.out[q] + L;
+        for (uint32_t k0 = 0; k0 < M; k0 += 64) {
+          uint32_t v[8];
 #pragma unroll
-          for (uint32_t u = 0; u < 4; u++) {
-            const uint32_t k = k0 + 64 * u + lane;
+          for (uint32_t u = 0; u < 8; u++) {
+            const uint32_t k = k0 + sub + 8 * u;
             v[u] = k < M ? src_byte(A, of + k, bad) : 0u;
           }
 #pragma unroll
-          for (uint32_t u = 0; u < 4; u++) {
-            const uint32_t k = k0 + 64 * u + lane;
+          for (uint32_t u = 0; u < 8; u++) {
+            const uint32_t k = k0 + sub + 8 * u;
             if (k < M && d0 + k < blen) S.tile[d0 + k] = (uint8_t)v[u];
           }
         }
@@ -516,11 +539,12 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
   // is read and it is final once every earlier match writing into it is done.
   // 4a: ordered list of these matches (ballot compaction, wave 0);
   // 4b: per match: destination, length, source (block-relative), period and
-  //     whether its window meets an earlier such match's destination
-  //     (binary search over the sorted destinations), packed into the
-  //     sequence tables, which are no longer needed;
-  // 4c: independent matches copied by all waves in parallel;
-  // 4d: dependent matches copied in order by wave 0, one LDS round trip each.
+  //     the range of earlier such matches whose destinations its window
+  //     meets (binary searches over the sorted destinations), packed into
+  //     the sequence tables, which are no longer needed;
+  // 4c: matches with an empty range copied by all waves in parallel;
+  // 4d: the others copied by wave 0 in passes, each pass the matches whose
+  //     earlier sources are complete.
   if (wv == 0) {
     uint32_t base = 0;
     for (uint32_t q0 = 0; q0 < ns; q0 += 64) {
@@ -564,21 +588,35 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
       S.out[a] = (uint16_t)mM[u];
     }
     __syncthreads();
-    // 4b phase 2: dependency test against earlier destinations
+    // 4b phase 2: the earlier matches whose destinations meet the window
+    // form an index range [lo, hi) (destinations are sorted and disjoint);
+    // the match is dependent if it is not empty.  The part of the range inside
+    // the match's own 64-entry chunk is kept as bit positions (plo, phi).
     for (uint32_t a = a0, u = 0; a < a1; a++, u++) {
       const int32_t s = (int32_t)ms[u] - 16384;
       const uint32_t w = min(md[u], mM[u]);
-      bool dep = false;
+      uint32_t lo = a, hi = a;
       if (s + (int32_t)w > 0) {
         const uint32_t ws = s > 0 ? (uint32_t)s : 0u, we = (uint32_t)(s + (int32_t)w);
         // first earlier match whose destination ends after ws
-        uint32_t lo = 0, hi = a;
-        while (lo < hi) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if ((uint32_t)S.lit[mid] + S.out[mid] > ws) hi = mid; else lo = mid + 1;
+        uint32_t l = 0, h = a;
+        while (l < h) {
+          const uint32_t mid = (l + h) >> 1;
+          if ((uint32_t)S.lit[mid] + S.out[mid] > ws) h = mid; else l = mid + 1;
         }
-        dep = lo < a && S.lit[lo] < we;
+        lo = l;
+        // first match from lo on whose destination starts at or after we
+        h = a;
+        while (l < h) {
+          const uint32_t mid = (l + h) >> 1;
+          if ((uint32_t)S.lit[mid] >= we) h = mid; else l = mid + 1;
+        }
+        hi = l;
       }
+      const bool dep = lo < hi;
+      const uint32_t c0 = a & ~63u;
+      const uint32_t plo = max(lo, c0) - c0, phi = max(hi, c0) - c0;   // both <= 63
+      S.intl[a] = (uint16_t)(plo | (phi << 8));
       S.oflo[a] = ms[u] | (md[u] << 16) | (dep ? 0x80000000u : 0u);
     }
   }
@@ -620,53 +658,68 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
     for (uint32_t a = wv; a < cnt; a += kWaves)
       if (!(S.oflo[a] & 0x80000000u)) copy_match(a);
     __syncthreads();
-    // 4d: dependent matches in order, wave 0 (LDS operations of one wave are
-    // performed in order, so each copy sees the previous ones).  Their
-    // entries are first moved to the front of the tables (an order-keeping
-    // compaction, in place: 64 entries are read before any is written, and a
-    // write never passes the read position); then each copy's source load is
-    // issued together with the next entry's loads, so a dependent chain pays
-    // one LDS round trip per match.
+    // 4d: dependent matches, wave 0, in passes over 64-entry chunks (every
+    // earlier chunk is complete).  Lane l holds the predecessor bits of entry
+    // c0 + l; a pass takes every pending match whose in-chunk predecessors
+    // are all done, which includes the lowest pending one, so a chunk takes
+    // at most 64 passes.  Matches of one pass do not read each other's
+    // destinations.  The pass's matches are listed in LDS and copied eight at
+    // a time, one per 8-lane slot, each lane every eighth byte (loads, then
+    // stores); a match longer than 64 bytes or shorter than its period is
+    // copied by the whole wave.  LDS operations of one wave are performed in
+    // order, so a pass sees every earlier pass.
     if (wv == 0) {
-      uint32_t nd = 0;
-      for (uint32_t a0 = 0; a0 < cnt; a0 += 64) {
-        const uint32_t a = a0 + lane;
-        uint32_t pk = 0, e0 = 0, eM = 0;
-        if (a < cnt) {
-          pk = S.oflo[a];
-          e0 = S.lit[a];
-          eM = S.out[a];
+      const uint32_t slot = lane >> 3, sub = lane & 7;
+      for (uint32_t c0 = 0; c0 < cnt; c0 += 64) {
+        const uint32_t a = c0 + lane;
+        const bool have = a < cnt;
+        const uint32_t rng = have ? (uint32_t)S.intl[a] : 0u;
+        const uint32_t plo = rng & 63u, phi = (rng >> 8) & 63u;
+        const uint64_t needm = phi > plo ? (1ull << phi) - (1ull << plo) : 0ull;
+        bool pending = have && (S.oflo[a] & 0x80000000u);
+        uint64_t done = ~__ballot(pending);
+        for (uint32_t pass = 0; pass <= 64; pass++) {
+          const bool ready = pending && (needm & ~done) == 0;
+          const uint64_t m = __ballot(ready);
+          if (!m) break;
+          pending = pending && !ready;
+          done |= m;
+          if (ready) S.plist[mbcnt(m)] = (uint8_t)lane;
+          __builtin_amdgcn_wave_barrier();
+          const uint32_t nr = (uint32_t)__popcll(m);
+          for (uint32_t g0 = 0; g0 < nr; g0 += 8) {
+            const uint32_t u = g0 + slot;
+            const bool sv = u < nr;
+            const uint32_t j = c0 + (sv ? (uint32_t)S.plist[u] : 0u);
+            const uint32_t pkj = S.oflo[j], dst = S.lit[j], len = S.out[j];
+            const int32_t sj = (int32_t)(pkj & 0xFFFFu) - 16384;
+            const uint32_t dj = (pkj >> 16) & 0x7FFFu;
+            const bool simple = sv && dj >= len && len <= 64;
+            uint32_t v[8];
+#pragma unroll
+            for (uint32_t q = 0; q < 8; q++) {
+              const uint32_t k = sub + 8 * q;
+              const int32_t src = sj + (int32_t)k;
+              v[q] = 0;
+              if (simple && k < len)
+                v[q] = src >= 0 ? (uint32_t)S.tile[(uint32_t)src & (kB - 1)]
+                                : src_byte(A, sb + (int64_t)src, bad);
+            }
+#pragma unroll
+            for (uint32_t q = 0; q < 8; q++) {
+              const uint32_t k = sub + 8 * q;
+              if (simple && k < len && dst + k < blen) S.tile[dst + k] = (uint8_t)v[q];
+            }
+            uint64_t slow = __ballot(sv && !simple && sub == 0);
+            while (slow) {                     // wave-uniform
+              const uint32_t l = (uint32_t)__builtin_ctzll(slow);
+              slow &= slow - 1;
+              copy_match((uint32_t)__builtin_amdgcn_readlane((int)j, (int)l));
+            }
+          }
+          __builtin_amdgcn_wave_barrier();
         }
-        const bool dep = a < cnt && (pk & 0x80000000u);
-        const uint64_t m = __ballot(dep);
-        __builtin_amdgcn_wave_barrier();
-        if (dep) {
-          const uint32_t j = nd + mbcnt(m);
-          S.oflo[j] = pk;
-          S.lit[j] = (uint16_t)e0;
-          S.out[j] = (uint16_t)eM;
-        }
-        nd += (uint32_t)__popcll(m);
-        __builtin_amdgcn_wave_barrier();
-      }
-      uint32_t pk = nd ? S.oflo[0] : 0u, e0 = nd ? S.lit[0] : 0u, eM = nd ? S.out[0] : 0u;
-      for (uint32_t j = 0; j < nd; j++) {
-        const int32_t sj = (int32_t)(pk & 0xFFFFu) - 16384;
-        const uint32_t dj = (pk >> 16) & 0x7FFFu;
-        const bool simple = sj >= 0 && dj >= eM && eM <= 64;
-        uint32_t v = 0;
-        if (simple && lane < eM) v = S.tile[(uint32_t)sj + lane];
-        const uint32_t jn = j + 1 < nd ? j + 1 : j;
-        const uint32_t pkn = S.oflo[jn], e0n = S.lit[jn], eMn = S.out[jn];
-        if (simple) {
-          if (lane < eM && e0 + lane < blen) S.tile[e0 + lane] = (uint8_t)v;
-        } else {
-          copy_match(j);
-        }
-        __builtin_amdgcn_wave_barrier();
-        pk = pkn;
-        e0 = e0n;
-        eM = eMn;
+        if (__ballot(pending)) bad = true;      // unreachable for a valid block
       }
     }
     if (bad) S.err = 1;
@@ -713,6 +766,13 @@ __device__ void load_tables(Smem& S, const DevArgs& A) {
       c += f[q];
     }
     if (lane == 63) S.cum[k][256] = (uint16_t)min(c, 65535u);
+  }
+  __syncthreads();
+  // bucket index of each short stream: bucket b starts at slot b << bs
+  for (uint32_t e = t; e < 3 * 256; e += kWG) {
+    const uint32_t k = e >> 8, b = e & 255, P = A.P[1 + k];
+    const uint32_t bs = P > 8 ? P - 8 : 0u;
+    if ((b << bs) < (1u << P)) S.bkt[k][b] = (uint8_t)search_sym(S.cum[k], b << bs);
   }
 }
 

@@ -92,6 +92,22 @@ def test_fasta_bit_exact(orc, lz):
         assert _decode(arc, mode) == x
 
 
+def test_many_in_block_matches(orc, lz):
+    """Hundreds of matches per 16 KiB block whose sources lie in the block
+    itself (a small vocabulary of 16..29-byte tokens), so the dependent
+    in-block matches span several 64-entry chunks and many passes."""
+    import numpy as np
+    rng = np.random.default_rng(7)
+    voc = [bytes(rng.integers(0, 256, int(rng.integers(16, 30)), dtype=np.uint8)) for _ in range(30)]
+    x = b"".join(voc[i] for i in rng.integers(0, 30, 4000))
+    p = dict(block_log2=14, min_match=16, hash_len=4, hash_bits=16, max_level=64, level_penalty=2)
+    seqs = np.bincount(orc.parse(x, **p)["blk"])
+    assert seqs.max() > 256
+    arc = lz.Archive(orc.encode(x, **p))
+    for mode in (0, 1):
+        assert _decode(arc, mode) == x
+
+
 def test_product_encoder_archive(orc, lz):
     """Archives from the library's own encoder decode to the source too."""
     from gen.fastq import fastq
