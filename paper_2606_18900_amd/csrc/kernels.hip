@@ -512,10 +512,16 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
         const uint32_t d0 = S.out[q] + L;
         for (uint32_t k0 = 0; k0 < M; k0 += 64) {
           uint32_t v[8];
+          if (!A.addr) {                       // whole-file output: one base, byte offsets
+            const uint8_t* p = A.out + of + k0 + sub;
 #pragma unroll
-          for (uint32_t u = 0; u < 8; u++) {
-            const uint32_t k = k0 + sub + 8 * u;
-            v[u] = k < M ? src_byte(A, of + k, bad) : 0u;
+            for (uint32_t u = 0; u < 8; u++) v[u] = k0 + sub + 8 * u < M ? (uint32_t)p[8 * u] : 0u;
+          } else {
+#pragma unroll
+            for (uint32_t u = 0; u < 8; u++) {
+              const uint32_t k = k0 + sub + 8 * u;
+              v[u] = k < M ? src_byte(A, of + k, bad) : 0u;
+            }
           }
 #pragma unroll
           for (uint32_t u = 0; u < 8; u++) {
@@ -696,14 +702,19 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
             const uint32_t dj = (pkj >> 16) & 0x7FFFu;
             const bool simple = sv && dj >= len && len <= 64;
             uint32_t v[8];
+            bool below = false;
 #pragma unroll
             for (uint32_t q = 0; q < 8; q++) {
-              const uint32_t k = sub + 8 * q;
-              const int32_t src = sj + (int32_t)k;
-              v[q] = 0;
-              if (simple && k < len)
-                v[q] = src >= 0 ? (uint32_t)S.tile[(uint32_t)src & (kB - 1)]
-                                : src_byte(A, sb + (int64_t)src, bad);
+              const int32_t src = sj + (int32_t)(sub + 8 * q);
+              v[q] = S.tile[(uint32_t)max(src, 0) & (kB - 1)];
+              below |= simple && sub + 8 * q < len && src < 0;
+            }
+            if (__ballot(below)) {
+#pragma unroll
+              for (uint32_t q = 0; q < 8; q++) {
+                const int32_t src = sj + (int32_t)(sub + 8 * q);
+                if (simple && sub + 8 * q < len && src < 0) v[q] = src_byte(A, sb + (int64_t)src, bad);
+              }
             }
 #pragma unroll
             for (uint32_t q = 0; q < 8; q++) {
@@ -776,7 +787,7 @@ __device__ void load_tables(Smem& S, const DevArgs& A) {
   }
 }
 
-__global__ void __launch_bounds__(kWG) k_decode(DevArgs A) {
+__global__ void __launch_bounds__(kWG, 3) k_decode(DevArgs A) {   // 3 waves per SIMD: at most 168 VGPRs
   __shared__ Smem S;
   const uint32_t t = threadIdx.x;
   load_tables(S, A);
