@@ -45,6 +45,7 @@ struct Smem {
   uint8_t ofhi[kMaxSeq + 3];   // bits 32..39
   uint16_t intl[kMaxSeq];      // matches whose source touches the block itself
   uint8_t plist[64];           // dependent matches of one pass (chunk-relative)
+  uint32_t ppk[64], pdl[64];   // their packed source/period and destination | length << 16
   uint16_t ring[kWaves][256];  // rANS words staged per wave (two 128-word slices)
   uint32_t ringe[kWaves][256]; // literal stream: table entry of each staged word's slot
   uint32_t scan[kWaves];
@@ -103,10 +104,14 @@ struct Stream {
 };
 
 // Parse and check the record at *off of a block payload; advances *off.
-__device__ __forceinline__ bool parse_stream(const uint8_t* pay, uint32_t plen, uint32_t* off,
-                                             uint32_t want, uint32_t maxK, Stream& s) {
-  if (*off + 16 > plen) return false;
-  const uint8_t* h = pay + *off;
+// Parses one stream record header from the LDS copy `hp` of the first hlen
+// payload bytes; records end within plen.  With `staged` the whole record must
+// lie in the copy (the short streams are decoded from it).
+__device__ __forceinline__ bool parse_stream(const uint8_t* hp, uint32_t hlen, uint32_t plen,
+                                             uint32_t* off, uint32_t want, uint32_t maxK,
+                                             bool staged, Stream& s) {
+  if (*off + 16 > hlen) return false;
+  const uint8_t* h = hp + *off;
   s.mode = h[0];
   s.csym = h[1];
   s.K = (uint32_t)h[2] | ((uint32_t)h[3] << 8);
@@ -115,6 +120,7 @@ __device__ __forceinline__ bool parse_stream(const uint8_t* pay, uint32_t plen, 
   s.blen = ld32(h + 12);
   s.body = *off + 16;
   if (s.n != want) return false;
+  if (staged && (uint64_t)s.body + s.blen > hlen) return false;
   switch (s.mode) {
     case kModeEmpty: if (s.n || s.blen) return false; break;
     case kModeConst: if (!s.n || s.blen) return false; break;
@@ -123,8 +129,9 @@ __device__ __forceinline__ bool parse_stream(const uint8_t* pay, uint32_t plen, 
       const uint32_t G = (s.K + 63) >> 6;
       if (s.K < 1 || s.K > maxK || !s.n || s.body + s.blen > plen) return false;
       if ((uint64_t)s.blen != 4ull * s.K + 4ull * G + 2ull * s.nw) return false;
+      if ((uint64_t)s.body + 4ull * s.K + 4ull * G > hlen) return false;
       uint64_t sum = 0;
-      for (uint32_t g = 0; g < G; g++) sum += ld32(pay + s.body + 4 * s.K + 4 * g);
+      for (uint32_t g = 0; g < G; g++) sum += ld32(hp + s.body + 4 * s.K + 4 * g);
       if (sum != s.nw) return false;
       break;
     }
@@ -367,14 +374,28 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
   const uint32_t plen = ld32(de + 8), ns = ld32(de + 12), nlit = ld32(de + 16);
   const uint8_t* pay = A.arc + A.off_payload + poff;
 
+  // The first min(plen, 16 KiB) payload bytes are copied into the tile (free
+  // until stage 3) with one round of 16-byte loads: the stream headers and
+  // the short streams CMD, MLEN, OFF (at most about 9.3 KB with their headers
+  // for 1025 sequences) are read from there; the literal stream from HBM.
+  const uint32_t hlen = min(plen, kB);
+  {
+    const uint4* src4 = reinterpret_cast<const uint4*>(pay);
+    uint4* dst4 = reinterpret_cast<uint4*>(S.tile);
+    for (uint32_t c = t; c < (hlen >> 4); c += kWG) dst4[c] = src4[c];
+    if (t < (hlen & 15u)) S.tile[(hlen & ~15u) + t] = pay[(hlen & ~15u) + t];
+  }
+  __syncthreads();
+  const uint8_t* hp = S.tile;
+
   // stream records: CMD, MLEN, OFF, LIT (every thread parses the same bytes)
   Stream sc, sm, so, sl;
   uint32_t off = 0;
   bool ok = ns >= 1 && ns <= kMaxSeq && nlit <= blen && (poff & 15) == 0;
-  ok = ok && parse_stream(pay, plen, &off, 2 * ns, A.seq_lanes, sc);
-  ok = ok && parse_stream(pay, plen, &off, 2 * ns, A.seq_lanes, sm);
-  ok = ok && parse_stream(pay, plen, &off, A.w * ns, A.seq_lanes, so);
-  ok = ok && parse_stream(pay, plen, &off, nlit, A.lit_lanes, sl);
+  ok = ok && parse_stream(hp, hlen, plen, &off, 2 * ns, A.seq_lanes, true, sc);
+  ok = ok && parse_stream(hp, hlen, plen, &off, 2 * ns, A.seq_lanes, true, sm);
+  ok = ok && parse_stream(hp, hlen, plen, &off, A.w * ns, A.seq_lanes, true, so);
+  ok = ok && parse_stream(hp, hlen, plen, &off, nlit, A.lit_lanes, false, sl);
   if (!ok) {
     if (t == 0) latch(A.ctl, kStCorrupt);
     return;
@@ -402,10 +423,10 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
     };
     bool okw = true;
     if (s.mode == kModeRans) {
-      okw = rans_group(pay + s.body, s, 0, A.P[1 + wv], S.ring[wv],
+      okw = rans_group(hp + s.body, s, 0, A.P[1 + wv], S.ring[wv],
                        [&](uint32_t u) { return bucket_sym(cum, S.bkt[wv], bs, u); }, put);
     } else if (s.mode == kModeRaw) {
-      const uint8_t* src = pay + s.body;
+      const uint8_t* src = hp + s.body;
       for (uint32_t i = lane; i < s.n; i += 64) put(i, src[i]);
     } else if (s.mode == kModeConst) {
       for (uint32_t i = lane; i < s.n; i += 64) put(i, s.csym);
@@ -682,7 +703,9 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
         const uint32_t rng = have ? (uint32_t)S.intl[a] : 0u;
         const uint32_t plo = rng & 63u, phi = (rng >> 8) & 63u;
         const uint64_t needm = phi > plo ? (1ull << phi) - (1ull << plo) : 0ull;
-        bool pending = have && (S.oflo[a] & 0x80000000u);
+        const uint32_t mpk = have ? S.oflo[a] : 0u;
+        const uint32_t mdl = have ? (uint32_t)S.lit[a] | ((uint32_t)S.out[a] << 16) : 0u;
+        bool pending = have && (mpk & 0x80000000u);
         uint64_t done = ~__ballot(pending);
         for (uint32_t pass = 0; pass <= 64; pass++) {
           const bool ready = pending && (needm & ~done) == 0;
@@ -690,14 +713,21 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
           if (!m) break;
           pending = pending && !ready;
           done |= m;
-          if (ready) S.plist[mbcnt(m)] = (uint8_t)lane;
+          if (ready) {                         // the pass's list, fields included
+            const uint32_t pos = mbcnt(m);
+            S.plist[pos] = (uint8_t)lane;
+            S.ppk[pos] = mpk;
+            S.pdl[pos] = mdl;
+          }
           __builtin_amdgcn_wave_barrier();
           const uint32_t nr = (uint32_t)__popcll(m);
           for (uint32_t g0 = 0; g0 < nr; g0 += 8) {
             const uint32_t u = g0 + slot;
             const bool sv = u < nr;
-            const uint32_t j = c0 + (sv ? (uint32_t)S.plist[u] : 0u);
-            const uint32_t pkj = S.oflo[j], dst = S.lit[j], len = S.out[j];
+            const uint32_t uu = sv ? u : 0u;
+            const uint32_t j = c0 + (uint32_t)S.plist[uu];
+            const uint32_t pkj = S.ppk[uu], dl = S.pdl[uu];
+            const uint32_t dst = dl & 0xFFFFu, len = dl >> 16;
             const int32_t sj = (int32_t)(pkj & 0xFFFFu) - 16384;
             const uint32_t dj = (pkj >> 16) & 0x7FFFu;
             const bool simple = sv && dj >= len && len <= 64;
