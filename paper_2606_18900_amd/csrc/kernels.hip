@@ -625,20 +625,19 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
       uint32_t lo = a, hi = a;
       if (s + (int32_t)w > 0) {
         const uint32_t ws = s > 0 ? (uint32_t)s : 0u, we = (uint32_t)(s + (int32_t)w);
-        // first earlier match whose destination ends after ws
-        uint32_t l = 0, h = a;
-        while (l < h) {
-          const uint32_t mid = (l + h) >> 1;
-          if ((uint32_t)S.lit[mid] + S.out[mid] > ws) h = mid; else l = mid + 1;
+        // two searches over [0, a) in lockstep: lo = first earlier match whose
+        // destination ends after ws, hi = first whose destination starts at
+        // or after we (hi >= lo: such a destination also ends after ws)
+        uint32_t l1 = 0, h1 = a, l2 = 0, h2 = a;
+        while (l1 < h1 || l2 < h2) {
+          const uint32_t m1 = (l1 + h1) >> 1, m2 = (l2 + h2) >> 1;
+          const uint32_t e1 = (uint32_t)S.lit[min(m1, a - 1)] + S.out[min(m1, a - 1)];
+          const uint32_t b2 = S.lit[min(m2, a - 1)];
+          if (l1 < h1) { if (e1 > ws) h1 = m1; else l1 = m1 + 1; }
+          if (l2 < h2) { if (b2 >= we) h2 = m2; else l2 = m2 + 1; }
         }
-        lo = l;
-        // first match from lo on whose destination starts at or after we
-        h = a;
-        while (l < h) {
-          const uint32_t mid = (l + h) >> 1;
-          if ((uint32_t)S.lit[mid] >= we) h = mid; else l = mid + 1;
-        }
-        hi = l;
+        lo = l1;
+        hi = l2;
       }
       const bool dep = lo < hi;
       const uint32_t c0 = a & ~63u;
