@@ -680,9 +680,17 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
         if (r >= d) r -= d;
       }
     };
-    // 4c: independent matches, all waves
-    for (uint32_t a = wv; a < cnt; a += kWaves)
-      if (!(S.oflo[a] & 0x80000000u)) copy_match(a);
+    // 4c: matches with an empty range, all waves: a wave tests 64 of its
+    // entries (a = wv + 4 l) at once, then copies the ones that qualify
+    for (uint32_t a0 = wv; a0 < cnt; a0 += kWaves * 64) {
+      const uint32_t a = a0 + kWaves * lane;
+      uint64_t m = __ballot(a < cnt && !(S.oflo[min(a, cnt - 1)] & 0x80000000u));
+      while (m) {                              // wave-uniform
+        const uint32_t l = (uint32_t)__builtin_ctzll(m);
+        m &= m - 1;
+        copy_match(a0 + kWaves * l);
+      }
+    }
     __syncthreads();
     // 4d: dependent matches, wave 0, in passes over 64-entry chunks (every
     // earlier chunk is complete).  Lane l holds the predecessor bits of entry
