@@ -1013,16 +1013,15 @@ int orc_decode_levels(const uint8_t* a, uint64_t len, uint8_t* out, uint64_t cap
 #pragma omp parallel num_threads(threads > 0 ? threads : 1) reduction(| : err)
 #endif
     {
+      /* every thread of the team reaches the worksharing loop; one whose
+       * scratch could not be allocated takes its iterations as failures */
       scratch_t s;
-      if (scratch_alloc(&v, &s)) {
-        err |= 1;
-      } else {
+      const int have = scratch_alloc(&v, &s) == 0;
 #ifdef _OPENMP
 #pragma omp for schedule(dynamic, 16)
 #endif
-        for (int64_t i = lo; i < hi; i++)
-          if (decode_block(&v, order[i], out, s.lit, s.cmd, s.mln, s.ofs)) err |= 1;
-      }
+      for (int64_t i = lo; i < hi; i++)
+        if (!have || decode_block(&v, order[i], out, s.lit, s.cmd, s.mln, s.ofs)) err |= 1;
       scratch_free(&s);
     }
   }

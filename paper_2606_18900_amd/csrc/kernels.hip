@@ -1051,7 +1051,7 @@ namespace {
 
 struct ReqArgs {
   const uint8_t* arc;
-  uint64_t n, off_dir, off_dep_ptr, off_dep_idx, off_ridx, n_reads;
+  uint64_t n, n_blocks, off_dir, off_dep_ptr, off_dep_idx, off_ridx, n_reads;
   uint32_t bl, mode, direct;
   uint64_t a0, b0;            // mode 0: the single range
   const int64_t* ids;         // mode 1: read ids
@@ -1099,8 +1099,19 @@ __device__ __forceinline__ void mark_push(const ReqArgs& R, uint32_t b, uint32_t
   __hip_atomic_store(R.list + i, ((uint64_t)epoch << 32) | b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void k_req_begin(ReqArgs R) {
+// One workgroup.  First the address-table entries of the previous call's
+// closure (still in the work list) are cleared, so that afterwards exactly the
+// blocks of this call's closure have an address: a match whose source lies in
+// any other block reads a null entry and fails as corrupt instead of following
+// a pointer into a buffer of an earlier call.  Then the counters are reset.
+__global__ void __launch_bounds__(256) k_req_begin(ReqArgs R) {
   const uint32_t t = threadIdx.x;
+  const uint32_t prev = min(R.ctl[kCtlListTail], (uint32_t)R.n_blocks);
+  for (uint32_t i = t; i < prev; i += blockDim.x) {
+    const uint32_t b = (uint32_t)R.list[i];
+    if (b < R.n_blocks) R.addr[b] = 0;
+  }
+  __syncthreads();
   if (t < 64) R.ctl[kCtlLevelCnt + t] = 0;
   if (t == 0) {
     R.ctl[kCtlREpoch] += 1;
@@ -1345,6 +1356,7 @@ int lz_launch_requests(lz_handle* h, const lz_request* d_reqs, const uint32_t* d
   ReqArgs R{};
   R.arc = v.base;
   R.n = v.n;
+  R.n_blocks = v.n_blocks;
   R.off_dir = v.off_dir;
   R.off_dep_ptr = v.off_dep_ptr;
   R.off_dep_idx = v.off_dep_idx;
@@ -1383,7 +1395,7 @@ int lz_launch_requests(lz_handle* h, const lz_request* d_reqs, const uint32_t* d
   const uint32_t spin = h->tune.spin_limit ? h->tune.spin_limit : (1u << 20);
   const uint32_t g_req = (uint32_t)std::min<uint64_t>(1024, (n_max + 255) / 256);
   const uint32_t g_wide = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(1024, (v.n_blocks + 255) / 256));
-  hipLaunchKernelGGL(k_req_begin, dim3(1), dim3(64), 0, s, R);
+  hipLaunchKernelGGL(k_req_begin, dim3(1), dim3(256), 0, s, R);
   hipLaunchKernelGGL(k_req_spans, dim3(g_req), dim3(256), 0, s, R);
   hipLaunchKernelGGL(k_req_scan, dim3(1), dim3(1024), 0, s, R);
   hipLaunchKernelGGL(k_req_mark, dim3(g_wide), dim3(256), 0, s, R);

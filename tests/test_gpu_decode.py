@@ -9,6 +9,7 @@ torch = pytest.importorskip("torch")
 
 
 def _decode(arc, mode, wg=2):
+    print("decode_all: sync_mode %d, wg_per_cu %d, %d blocks" % (mode, wg, arc.n_blocks), flush=True)
     arc.set_tuning(sync_mode=mode, wg_per_cu=wg)
     out = arc.decode_all()
     torch.cuda.synchronize()
@@ -126,3 +127,27 @@ def test_empty_and_tiny(orc, lz):
         torch.cuda.synchronize()
         arc.sync_status()
         assert out.cpu().numpy().tobytes()[: len(x)] == x
+
+
+def test_blocks_at_the_sequence_cap(orc, lz):
+    """16 KiB blocks of 1024 back-to-back 16-byte matches each (the most that
+    m = 16 allows), about a third of them copying from earlier matches of the
+    same block: whole-file decode in both modes and range decodes equal the
+    source."""
+    from gen.tokens import token_stream
+    x = token_stream(6)
+    p = dict(block_log2=14, min_match=16, hash_len=16, hash_bits=20, max_level=64,
+             level_penalty=0)
+    assert list(np.bincount(orc.parse(x, **p)["blk"]))[1:] == [1024] * 5
+    a = orc.encode(x, **p)
+    arc = lz.Archive(a)
+    for mode in (0, 1):
+        assert _decode(arc, mode) == x
+    B = 1 << 14
+    for o, L in ((B, 3 * B), (2 * B + 5, B), (5 * B - 17, 17)):
+        out = torch.empty(L + 64, dtype=torch.uint8, device="cuda")
+        scratch = torch.full((arc.scratch_bytes(1),), 0xAA, dtype=torch.uint8, device="cuda")
+        arc.decode_range(o, L, out=out, scratch=scratch)
+        torch.cuda.synchronize()
+        arc.sync_status()
+        assert out[:L].cpu().numpy().tobytes() == x[o:o + L]

@@ -225,3 +225,59 @@ def test_batcher_graph_replays(fq):
         torch.cuda.synchronize()
         arc.decode_range(100, 5000)
         _sync(arc)
+
+
+def test_stream_range_windows_reach_evicted_blocks(orc, small):
+    """Windowed range streaming: windows of 1000 bytes (not a block multiple,
+    so windows split blocks) over the 64-byte-block archive with deep
+    dependencies.  Later windows need blocks of windows already dropped; those
+    are decoded again into the 0xAA-poisoned scratch.  Every window equals the
+    oracle's range decode and the source, in both launch modes."""
+    x, arc = small
+    a = bytes(arc.d_archive.cpu().numpy())
+    N, win = len(x), 1000
+    # the oracle confirms that windows reach back into earlier windows
+    reach = 0
+    for o in range(0, N, win):
+        L = min(win, N - o)
+        rc, ref, closure = orc.decode_range(a, o, L)
+        assert rc == 0 and ref == x[o:o + L]
+        covering = (o + L - 1) // 64 - o // 64 + 1
+        reach += closure > covering
+    assert reach >= 3
+    for mode in (1, 0):
+        arc.set_tuning(sync_mode=mode)
+        wbuf = torch.full((win + 64,), 0x55, dtype=torch.uint8, device="cuda")
+        scratch = torch.full((arc.scratch_bytes(1),), 0xAA, dtype=torch.uint8, device="cuda")
+        n_win = 0
+        for o, view in arc.stream_range(0, N, win, out=wbuf, scratch=scratch):
+            got = view.cpu().numpy().tobytes()
+            arc.sync_status()
+            assert got == x[o:o + view.numel()], (mode, o)
+            n_win += 1
+        assert n_win == -(-N // win)
+
+
+def test_range_with_swapped_dependency_is_corrupt(orc, lz):
+    """A block whose dependency list names the wrong source block (all list
+    and level checks still pass, so lz_open accepts the archive): a range
+    decode of that block must report LZ_ECORRUPT, never read a block outside
+    the call's dependency closure, and leave the handle usable."""
+    from gen.fastq import fastq
+    from tests.ref.tamper import swap_dependency
+    x, _ = fastq(n_records=3000, seed=1)
+    t, b, d, d2 = swap_dependency(orc.encode(x, kind=1, level_penalty=32))
+    arc = lz.Archive(t)
+    B = 1 << 14
+    for mode in (1, 0):
+        arc.set_tuning(sync_mode=mode)
+        # decode the wrongly omitted block first, so its address-table entry
+        # holds a pointer from an earlier call
+        assert _range(arc, d * B, 100, mode) == x[d * B:d * B + 100]
+        out = torch.empty(B, dtype=torch.uint8, device="cuda")
+        scratch = torch.full((arc.scratch_bytes(1),), 0xAA, dtype=torch.uint8, device="cuda")
+        arc.decode_range(b * B, B, out=out, scratch=scratch)
+        with pytest.raises(lz.LzError) as e:
+            _sync(arc)
+        assert e.value.code == lz._lib.LZ_ECORRUPT
+        assert _range(arc, 0, 1000, mode) == x[:1000]
