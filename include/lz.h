@@ -18,8 +18,10 @@
  *  - Every function returns an int status: LZ_OK (0) or a negative LZ_E* code;
  *    lz_last_error() gives the text of the last failure of the calling thread.
  *  - The caller owns every device buffer (archive, workspace, outputs,
- *    scratch); the library never allocates device memory.  A handle keeps
- *    non-owning pointers to the archive and workspace, which must outlive it.
+ *    scratch); the library never allocates device memory.  The one device
+ *    buffer it holds is the fixed scratch array of lz_read_lookup_noalloc,
+ *    part of its code object.  A handle keeps non-owning pointers to the
+ *    archive and workspace, which must outlive it.
  *  - Device calls are asynchronous on the caller's HIP stream `s` (may be 0).
  *    Arguments are checked on the host before anything is enqueued; errors
  *    found by a kernel (corrupt payload, scratch exhausted, watchdog) are
@@ -151,6 +153,22 @@ int lz_decode_range(lz_handle* h, uint64_t offset, uint64_t len, uint8_t* d_out,
 int lz_read_lookup(lz_handle* h, const int64_t* d_ids, uint64_t n, uint8_t* d_out,
                    uint64_t cap, uint64_t* d_offsets, void* d_scratch,
                    uint64_t scratch_len, hipStream_t s);
+
+/* Allocation-free read lookup, for callers that cannot allocate device memory
+ * per call (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same result as lz_read_lookup, but the request scratch
+ * is a fixed array of LZ_NOALLOC_SCRATCH_BYTES that the library holds in
+ * device memory, one per GPU, for the life of the process.  n is at most
+ * LZ_NOALLOC_MAX_IDS (ECAPACITY otherwise); a dependency closure needing more
+ * block slots than the array holds after the per-request tables (2039 slots of
+ * 16 KiB) is latched as ECAPACITY.  The current device must be the one the
+ * handle was opened on.  Every call on a GPU shares that GPU's array: calls
+ * that overlap in time on one GPU (any handle, any stream) race and must be
+ * ordered by the caller.  No device or host allocation is made by the call. */
+#define LZ_NOALLOC_SCRATCH_BYTES (32u << 20)
+#define LZ_NOALLOC_MAX_IDS 4096
+int lz_read_lookup_noalloc(lz_handle* h, const int64_t* d_ids, uint64_t n, uint8_t* d_out,
+                           uint64_t cap, uint64_t* d_offsets, hipStream_t s);
 
 /* Batched requests (mixed reads and ranges) resolved together: one closure
  * over all requests, one decode launch over the shared level-ordered queue,

@@ -11,13 +11,14 @@ LIB_PATH = os.path.join(HERE, "liblz.so")
 
 LZ_OK, LZ_EINVAL, LZ_EFORMAT, LZ_ECAPACITY, LZ_ERANGE = 0, -1, -2, -3, -4
 LZ_ENOINDEX, LZ_EDEVICE, LZ_ECORRUPT, LZ_EBUDGET = -5, -6, -7, -8
+NOALLOC_SCRATCH_BYTES, NOALLOC_MAX_IDS = 32 << 20, 4096   # lz.h LZ_NOALLOC_*
 NAMES = {0: "LZ_OK", -1: "LZ_EINVAL", -2: "LZ_EFORMAT", -3: "LZ_ECAPACITY", -4: "LZ_ERANGE",
          -5: "LZ_ENOINDEX", -6: "LZ_EDEVICE", -7: "LZ_ECORRUPT", -8: "LZ_EBUDGET"}
 
 # every symbol include/lz.h declares
 EXPORTS = ["lz_params_default", "lz_encode", "lz_free", "lz_info_get", "lz_open", "lz_close",
            "lz_get_info", "lz_set_tuning", "lz_get_tuning", "lz_decode_all", "lz_decode_range",
-           "lz_read_lookup", "lz_decode_batch", "lz_verify", "lz_sync_status", "lz_last_error"]
+           "lz_read_lookup", "lz_read_lookup_noalloc", "lz_decode_batch", "lz_verify", "lz_sync_status", "lz_last_error"]
 
 
 class LzError(RuntimeError):
@@ -76,6 +77,7 @@ def lib():
         L.lz_decode_all.argtypes = [vp, vp, u64, vp]
         L.lz_decode_range.argtypes = [vp, u64, u64, vp, vp, u64, vp]
         L.lz_read_lookup.argtypes = [vp, vp, u64, vp, u64, vp, vp, u64, vp]
+        L.lz_read_lookup_noalloc.argtypes = [vp, vp, u64, vp, u64, vp, vp]
         L.lz_decode_batch.argtypes = [vp, vp, vp, u64, vp, u64, vp, vp, u64, vp]
         L.lz_verify.argtypes = [vp, vp, vp, vp, u64, vp]
         L.lz_sync_status.argtypes = [vp, vp]

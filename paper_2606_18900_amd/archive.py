@@ -159,6 +159,16 @@ class Archive:
                                    _ptr(scratch), scratch.numel(), _stream(stream)))
         return out, offsets
 
+    def read_lookup_noalloc(self, ids: torch.Tensor, out: torch.Tensor, offsets: torch.Tensor,
+                            stream=None):
+        """lz_read_lookup_noalloc: read lookup whose request scratch is the
+        library's fixed device array (no allocation by the call; ids, out and
+        offsets are the caller's device tensors)."""
+        assert ids.dtype == torch.int64 and ids.is_contiguous()
+        check(lib().lz_read_lookup_noalloc(self.h, _ptr(ids), ids.numel(), _ptr(out), out.numel(),
+                                           _ptr(offsets), _stream(stream)))
+        return out, offsets
+
     def decode_batch(self, reqs: torch.Tensor, n: torch.Tensor, n_max: int, out: torch.Tensor,
                      offsets: torch.Tensor, scratch: torch.Tensor, stream=None):
         """reqs: device int64 [n_max, 3] rows (kind, a, b); n: device int32 [1]

@@ -81,6 +81,7 @@ struct lz_handle {
   Workspace ws;
   lz_tuning tune;
   int n_cu;
+  int dev;                            // device the handle was opened on
   uint32_t level_count[kMaxLevels];   // host copy of the whole-file level histogram
   uint64_t literal_bytes;             // sum of n_lit over blocks
   uint64_t payload_bytes;             // end of the last block payload

@@ -29,6 +29,7 @@ size_t lz_decode_smem_bytes();
 int lz_launch_setup(lz_handle* h, hipStream_t s);
 int lz_launch_decode_all(lz_handle* h, uint8_t* out, hipStream_t s);
 int lz_launch_verify(lz_handle* h, const uint8_t* d_out, uint64_t* d_tree, void* scratch, hipStream_t s);
+int lz_noalloc_setup(int dev, void** ptr);
 int lz_launch_requests(lz_handle* h, const lz_request* d_reqs, const uint32_t* d_n, uint64_t n_max,
                        uint64_t single_off, uint64_t single_len, const int64_t* d_ids,
                        uint8_t* d_out, uint64_t cap, uint64_t* d_offsets, void* d_scratch,
@@ -268,6 +269,11 @@ extern "C" int lz_open(const uint8_t* d_archive, uint64_t len, void* d_ws, uint6
   if (!rc) rc = hip_check(hipGetDeviceProperties(&prop, dev), "lz_open: properties");
   if (rc) { delete h; return rc; }
   h->n_cu = prop.multiProcessorCount;
+  h->dev = dev;
+  {
+    void* p = nullptr;   // resolve this device's allocation-free scratch once
+    if ((rc = lz_noalloc_setup(dev, &p))) { delete h; return rc; }
+  }
 
   // level-ordered queue of the whole file (ascending block id inside a level)
   std::vector<uint32_t> lptr(65, 0), queue(std::max<uint64_t>(nb, 1));
