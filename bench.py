@@ -240,6 +240,39 @@ def serve_leg(args, arq, xq, starts) -> int:
     return 0
 
 
+STAGES = ["payload copy", "stream headers", "short streams (CMD, MLEN, OFF)",
+          "block scan, match lists", "literal decode and placement", "matches from earlier blocks",
+          "in-block match fields and ranges", "in-block match passes", "tile store"]
+
+
+def stage_clocks(arc, out) -> int:
+    """Cycles per block of each decode-kernel stage, summed over all
+    workgroups of one whole-file decode (per-level launches) by the
+    instrumented build; printed as a table on stderr."""
+    import torch
+    ctl_off = int(arc.info.workspace_bytes) - 512          # control words: last section
+    clk = arc.ws[ctl_off + 4 * 96: ctl_off + 4 * 96 + 8 * 16]
+    arc.set_tuning(sync_mode=0, wg_per_cu=3)
+    arc.decode_all(out)
+    torch.cuda.synchronize()
+    clk.zero_()
+    arc.decode_all(out)
+    torch.cuda.synchronize()
+    arc.sync_status()
+    v = clk.cpu().view(torch.int64).tolist()
+    blocks = max(1, v[9])
+    log("stage clocks, %d blocks (cycles per block, summed over the 256 threads' barriers):" % v[9])
+    tot = 0
+    for i, name in enumerate(STAGES):
+        log("  %-36s %8.0f" % (name, v[i] / blocks))
+        tot += v[i]
+    log("  %-36s %8.0f" % ("total", tot / blocks))
+    log("  wave 0, per block: %.2f in-block passes, %.2f slow in-block matches taking %.0f cycles; "
+        "%.2f literal ring refills taking %.0f cycles" % (v[10] / blocks, v[11] / blocks, v[12] / blocks,
+                                                        v[14] / blocks, v[13] / blocks))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -257,7 +290,13 @@ def main() -> int:
                     help="output window of the genome leg's range streaming")
     ap.add_argument("--cache", default=None,
                     help="directory for the encoded archive: reused when present")
+    ap.add_argument("--stage-clocks", action="store_true",
+                    help="load the instrumented library (liblz_clk.so), decode once per "
+                         "level launch mode and print cycles per block for each kernel stage; "
+                         "no bench line")
     args = ap.parse_args()
+    if args.stage_clocks:
+        os.environ["LZ_STAGE_CLOCKS"] = "1"
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the decode path has no "
               "multi-GPU sharding); use --gpus 1", file=sys.stderr)
@@ -322,6 +361,9 @@ def main() -> int:
             log("FNV tree mismatch (mode %d)" % mode)
             return 1
     log("decoded output bit-exact vs source (%d bytes), device FNV tree ok" % N)
+
+    if args.stage_clocks:
+        return stage_clocks(arc, out)
 
     def run(mode: int, wg: int, steps: int, warmup: int):
         arc.set_tuning(sync_mode=mode, wg_per_cu=wg)

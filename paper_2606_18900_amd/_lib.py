@@ -7,7 +7,9 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblz.so")
+# LZ_STAGE_CLOCKS=1 loads the instrumented build (liblz_clk.so, built by
+# `python -m paper_2606_18900_amd.build --stage-clocks`) for stage profiling.
+LIB_PATH = os.path.join(HERE, "liblz_clk.so" if os.environ.get("LZ_STAGE_CLOCKS") == "1" else "liblz.so")
 
 LZ_OK, LZ_EINVAL, LZ_EFORMAT, LZ_ECAPACITY, LZ_ERANGE = 0, -1, -2, -3, -4
 LZ_ENOINDEX, LZ_EDEVICE, LZ_ECORRUPT, LZ_EBUDGET = -5, -6, -7, -8

@@ -9,6 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INC = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "liblz.so")
+LIB_CLK = os.path.join(HERE, "liblz_clk.so")   # instrumented variant (stage clocks)
 SOURCES = ["kernels.hip", "noalloc.hip", "runtime.cpp", "encode.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
@@ -16,14 +17,18 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-I", INC, "-I", CSRC]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, stage_clocks: bool = False) -> str:
+    """Build liblz.so; with stage_clocks, the instrumented variant
+    liblz_clk.so (per-stage cycle counters of the decode kernel)."""
     objs = []
-    bdir = os.path.join(HERE, "_build")
+    bdir = os.path.join(HERE, "_build_clk" if stage_clocks else "_build")
+    lib = LIB_CLK if stage_clocks else LIB
+    extra = ["-DLZ_STAGE_CLOCKS"] if stage_clocks else []
     os.makedirs(bdir, exist_ok=True)
     procs = []
     for s in SOURCES:
         o = os.path.join(bdir, s + ".o")
-        cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, s), "-o", o]
+        cmd = [HIPCC] + FLAGS + extra + ["-x", "hip", "-c", os.path.join(CSRC, s), "-o", o]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((s, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -37,12 +42,12 @@ def build(verbose: bool = False) -> str:
             fail.append(s)
     if fail:
         raise RuntimeError("hipcc failed on " + ", ".join(fail))
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, stage_clocks="--stage-clocks" in sys.argv))

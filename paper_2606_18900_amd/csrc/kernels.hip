@@ -1,18 +1,22 @@
 // Device decoder for container format v2 on gfx950 (CDNA4, wave64).
 //
-// One workgroup of 256 threads (4 waves) decodes one block at a time:
+// One workgroup of 256 threads (4 waves) decodes one 16 KiB block at a time
+// into an LDS tile:
+//   0. one round of 16-byte loads copies the block's payload prefix into the
+//      tile; the four stream headers are parsed from that copy;
 //   1. waves 0..2 decode the command (CMD), match-length (MLEN) and offset
-//      (OFF) streams, one each, reading rANS words straight from HBM;
-//   2. block-wide exclusive scans turn literal-run and match lengths into
-//      literal and output positions (command placement);
-//   3. the literal stream's 64-lane groups are decoded by one wave each and
-//      every literal is written straight to its output position in an LDS tile;
-//   4. matches whose source lies wholly in earlier blocks are copied in
-//      parallel; then the remaining matches are copied in order, each with
-//      out[p+k] = out[OF + (k mod (p-OF))], the byte-sequential overlap rule
-//      out[p+k] = out[OF+k] unrolled, so all bytes of a match go at once;
-//   5. the tile is written to HBM with 16-byte stores and, in the persistent
-//      kernel, the block's completion flag is released.
+//      (OFF) streams, one each, reading their rANS words from the LDS copy;
+//   2. one block-wide scan turns literal-run and match lengths into literal
+//      and output positions (command placement), counts the matches whose
+//      source touches the block itself in sequence order, and lists the
+//      matches whose source lies wholly in earlier blocks;
+//   3. the literal stream's 64-lane groups are decoded by one wave each, every
+//      literal written straight to its output position in the tile; then the
+//      matches from earlier blocks are copied from HBM;
+//   4. the matches whose source touches the block are resolved in dependency
+//      passes: a match is copied once every earlier match that writes into its
+//      source window is done; byte-sequential overlap is unrolled by period;
+//   5. the tile is written to HBM with 16-byte stores.
 // Blocks are taken in dependency-level order ("wavefront" order, paper:
 // Background section), either one launch per level or one persistent launch
 // whose workgroups take tickets and wait on the flags of a block's
@@ -25,31 +29,63 @@
 
 namespace {
 
-constexpr int kWG = 256;
-constexpr int kWaves = kWG / 64;
+constexpr uint32_t kWG = 256;
+constexpr uint32_t kWaves = kWG / 64;
 constexpr uint32_t kB = 1u << kMaxBlockLog2;      // largest block: 16 KiB tile
 constexpr uint32_t kMaxSeq = 1025;                // B/m + 1 for B = 16 KiB, m = 16
 constexpr uint32_t kLutLit = 1u << kMaxPLit;      // 4096 packed literal entries
 constexpr uint32_t kL = 1u << 16;                 // rANS state lower bound
+constexpr uint32_t kFastLen = 64;                 // in-block matches copied by one lane
+constexpr uint32_t kClkSlots = 16;                // stage clocks: 9 stages, block count, events
 
-// All LDS is static (about 51.8 KB, three workgroups per CU): literal LUT,
-// output tile, small-stream cumulative tables, per-sequence tables.
+// Stage clocks (instrumented build only, -DLZ_STAGE_CLOCKS): a barrier, then
+// thread 0 adds the cycles since the previous mark to stage i.  The product
+// build compiles these to nothing.
+#ifdef LZ_STAGE_CLOCKS
+#define CLK_START(S) do { if (threadIdx.x == 0) (S).clk_last = __builtin_readcyclecounter(); } while (0)
+#define CLK_MARK(S, i)                                          \
+  do {                                                          \
+    __syncthreads();                                            \
+    if (threadIdx.x == 0) {                                     \
+      const uint64_t c_ = __builtin_readcyclecounter();         \
+      (S).clk[i] += c_ - (S).clk_last;                          \
+      (S).clk_last = c_;                                        \
+    }                                                           \
+  } while (0)
+// event counters of lane 0 of wave 0 (slots 10..15): CLK_ADD(S, i, v)
+#define CLK_ADD(S, i, v) do { if (threadIdx.x == 0) (S).clk[i] += (v); } while (0)
+#define CLK_NOW() __builtin_readcyclecounter()
+#else
+#define CLK_START(S) do { } while (0)
+#define CLK_MARK(S, i) do { } while (0)
+#define CLK_ADD(S, i, v) do { } while (0)
+#define CLK_NOW() 0ull
+#endif
+
+// All LDS is static (53,240 B: three workgroups per CU).
 struct Smem {
-  uint32_t lut[kLutLit];
-  alignas(16) uint8_t tile[kB];
+  uint32_t lut[kLutLit];       // literal decode entries: symbol | f << 8 | (slot - c) << 20
+  alignas(16) uint8_t tile[kB];// output tile; until stage 3 a copy of the payload prefix
   uint16_t cum[3][257];        // CMD, MLEN, OFF cumulative frequencies
   uint8_t bkt[3][256];         // per stream: symbol owning the first slot of each bucket
-  uint16_t lit[kMaxSeq + 1];   // LL values, then exclusive scan of LL ([ns] = n_lit)
-  uint16_t out[kMaxSeq + 1];   // ML values, then exclusive scan of LL+ML ([ns] = block length)
-  uint32_t oflo[kMaxSeq];      // absolute source offsets, low 32 bits
-  uint8_t ofhi[kMaxSeq + 3];   // bits 32..39
-  uint16_t intl[kMaxSeq];      // matches whose source touches the block itself
-  uint8_t plist[64];           // dependent matches of one pass (chunk-relative)
-  uint32_t ppk[64], pdl[64];   // their packed source/period and destination | length << 16
-  uint16_t ring[kWaves][256];  // rANS words staged per wave (two 128-word slices)
-  uint32_t ringe[kWaves][256]; // literal stream: table entry of each staged word's slot
-  uint32_t scan[kWaves];
-  uint32_t item, err, nint;
+  uint16_t lit[kMaxSeq + 1];   // LL, then literal start of each sequence ([ns] = n_lit);
+                               // stage 4: destination of in-block match a
+  uint16_t out[kMaxSeq + 1];   // ML, then output start of each sequence ([ns] = block length);
+                               // stage 4: length of in-block match a
+  uint32_t oflo[kMaxSeq];      // absolute source offsets, low 32 bits; stage 4: packed
+                               // source, period and dependency flag of in-block match a
+  uint8_t ofhi[kMaxSeq + 3];   // offset bits 32..39
+  uint16_t lst[kMaxSeq];       // [0, n_ext): matches from earlier blocks (any order);
+                               // [kMaxSeq - n_in, kMaxSeq): in-block matches, last first;
+                               // stage 4: dependency range of in-block match a
+  uint16_t ring[kWaves][256];  // rANS words of the literal stream staged per wave
+  uint32_t ringe[kWaves][256]; // table entry of each staged word's slot
+  uint32_t dummy[64];          // target of the masked-off lanes' byte stores
+  uint32_t scan[3][kWaves];
+  uint32_t item, err, next, nin;
+#ifdef LZ_STAGE_CLOCKS
+  uint64_t clk[kClkSlots], clk_last;
+#endif
 };
 
 struct DevArgs {
@@ -77,6 +113,7 @@ __device__ __forceinline__ uint64_t ld64(const uint8_t* p) {
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 __device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -98,26 +135,31 @@ __device__ __forceinline__ void watchdog(uint32_t* ctl, uint32_t site, uint32_t 
   ctl[kCtlDiag + 4] = want;
 }
 
-// One stream record, parsed by every thread from global memory (uniform).
+// True once any wait of the current call has timed out: every later wait
+// gives up at once, so a call that cannot finish ends after one time-out.
+__device__ __forceinline__ bool watchdog_fired(const uint32_t* ctl) {
+  return __hip_atomic_load(const_cast<uint32_t*>(ctl) + kCtlStatus, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kStWatchdog;
+}
+
+// One stream record header (wave-uniform fields).
 struct Stream {
   uint32_t mode, csym, K, n, nw, blen, body;
 };
 
-// Parse and check the record at *off of a block payload; advances *off.
-// Parses one stream record header from the LDS copy `hp` of the first hlen
-// payload bytes; records end within plen.  With `staged` the whole record must
-// lie in the copy (the short streams are decoded from it).
+// Parse and check the record at *off (16-byte aligned) of the LDS copy `hp` of
+// the first hlen payload bytes; records end within plen.  With `staged` the
+// whole record must lie in the copy (the short streams are decoded from it).
 __device__ __forceinline__ bool parse_stream(const uint8_t* hp, uint32_t hlen, uint32_t plen,
                                              uint32_t* off, uint32_t want, uint32_t maxK,
                                              bool staged, Stream& s) {
   if (*off + 16 > hlen) return false;
-  const uint8_t* h = hp + *off;
-  s.mode = h[0];
-  s.csym = h[1];
-  s.K = (uint32_t)h[2] | ((uint32_t)h[3] << 8);
-  s.n = ld32(h + 4);
-  s.nw = ld32(h + 8);
-  s.blen = ld32(h + 12);
+  const uint4 h = *reinterpret_cast<const uint4*>(hp + *off);
+  s.mode = uni(h.x & 0xFFu);
+  s.csym = uni((h.x >> 8) & 0xFFu);
+  s.K = uni(h.x >> 16);
+  s.n = uni(h.y);
+  s.nw = uni(h.z);
+  s.blen = uni(h.w);
   s.body = *off + 16;
   if (s.n != want) return false;
   if (staged && (uint64_t)s.body + s.blen > hlen) return false;
@@ -130,8 +172,9 @@ __device__ __forceinline__ bool parse_stream(const uint8_t* hp, uint32_t hlen, u
       if (s.K < 1 || s.K > maxK || !s.n || s.body + s.blen > plen) return false;
       if ((uint64_t)s.blen != 4ull * s.K + 4ull * G + 2ull * s.nw) return false;
       if ((uint64_t)s.body + 4ull * s.K + 4ull * G > hlen) return false;
+      const uint32_t* cnt = reinterpret_cast<const uint32_t*>(hp + s.body + 4 * s.K);
       uint64_t sum = 0;
-      for (uint32_t g = 0; g < G; g++) sum += ld32(hp + s.body + 4 * s.K + 4 * g);
+      for (uint32_t g = 0; g < G; g++) sum += uni(cnt[g]);
       if (sum != s.nw) return false;
       break;
     }
@@ -139,212 +182,6 @@ __device__ __forceinline__ bool parse_stream(const uint8_t* hp, uint32_t hlen, u
   }
   *off = s.body + ((s.blen + 15u) & ~15u);
   return true;
-}
-
-// Decode the symbols of 64-lane group g of a rANS stream with one wave.
-// `body` is the record body in global memory (states, per-group word counts,
-// words).  `sym(u)` maps slot u to symbol | f << 8 | (u - c_s) << 20 and
-// `out(i, s)` consumes symbol i.  The group's 16-bit words are staged through
-// the wave's LDS ring (two 128-word slices, the next slice loading into
-// registers meanwhile), so a lane needing word idx reads it from LDS.
-// True if every state ends at 2^16 and every word of the group was read.
-template <class Sym, class Out>
-__device__ bool rans_group(const uint8_t* body, const Stream& s, uint32_t g, uint32_t P,
-                           uint16_t* ring, Sym&& sym, Out&& out) {
-  const uint32_t lane = lane_id();
-  const uint32_t K = s.K, n = s.n, G = (K + 63) >> 6;
-  const uint32_t k = (g << 6) + lane;
-  const bool lane_ok = k < K;
-  uint32_t woff = 0, nwg = 0;
-  for (uint32_t q = 0; q < G; q++) {
-    const uint32_t c = ld32(body + 4 * K + 4 * q);
-    if (q < g) woff += c;
-    if (q == g) nwg = c;
-  }
-  // Word loads are unconditional: an index past the group's end reads the
-  // group's last word (or, for a group without words, the first state), so
-  // every load stays inside the record; a corrupt stream that consumes more
-  // words than the group holds fails the end check (pos == nwg).
-  const uint16_t* W = nwg ? reinterpret_cast<const uint16_t*>(body + 4 * K + 4 * G) + woff
-                          : reinterpret_cast<const uint16_t*>(body);
-  const uint32_t lastw = nwg ? nwg - 1 : 0;
-  auto ldw = [&](uint32_t idx) -> uint32_t { return (uint32_t)W[min(idx, lastw)]; };
-  uint32_t x = lane_ok ? ld32(body + 4 * k) : kL;
-  bool ok = x >= kL && woff + nwg <= s.nw;
-  // Ring of two 128-word slices: with s = pos / 128, slices s and s+1 are in
-  // the ring and slice s+2 is in flight in registers (pa, pb).
-  {
-    const uint32_t a0 = ldw(lane), a1 = ldw(64 + lane), a2 = ldw(128 + lane), a3 = ldw(192 + lane);
-    ring[lane] = (uint16_t)a0;
-    ring[64 + lane] = (uint16_t)a1;
-    ring[128 + lane] = (uint16_t)a2;
-    ring[192 + lane] = (uint16_t)a3;
-  }
-  uint32_t pa = ldw(256 + lane), pb = ldw(320 + lane);
-  uint32_t pos = 0;
-  // lane k decodes the run of consecutive symbols starting at
-  // k*full + min(k, extra): full = n / K symbols, one more for the first
-  // extra = n mod K lanes
-  const uint32_t full = n / K, extra = n - full * K;
-  const uint32_t mask = (1u << P) - 1;
-  uint32_t i = k * full + min(k, extra);
-  auto round = [&](bool act) {
-    if (act) {
-      const uint32_t e = sym(x & mask);
-      x = __umul24((e >> 8) & 0xFFFu, x >> P) + (e >> 20);
-      out(i, e & 0xFFu);
-    }
-    i += 1;
-    const bool need = act && x < kL;
-    const uint64_t bal = __ballot(need);
-    if (bal) {
-      if (need) x = (x << 16) | (uint32_t)ring[(pos + mbcnt(bal)) & 255];
-      const uint32_t s0 = pos >> 7;
-      pos += (uint32_t)__popcll(bal);
-      if ((pos >> 7) != s0) {          // entered slice s0+1: stage s0+2, fetch s0+3
-        __builtin_amdgcn_wave_barrier();   // after every lane's read of slice s0
-        uint16_t* d = ring + ((s0 & 1) << 7) + lane;
-        d[0] = (uint16_t)pa;
-        d[64] = (uint16_t)pb;
-        const uint32_t b3 = (s0 + 3) << 7;
-        pa = ldw(b3 + lane);
-        pb = ldw(b3 + 64 + lane);
-      }
-    }
-  };
-  // rounds in which every lane of the stream decodes, then the partial one
-  for (uint32_t r = 0; r < full; r++) round(lane_ok);
-  if (extra) round(lane_ok && k < extra);
-  ok = ok && (!lane_ok || x == kL) && pos == nwg;
-  return __ballot(!ok) == 0;
-}
-
-// The literal stream's group decode: the same symbols, words and checks as
-// rans_group, with the next table lookup of a renormalising lane folded into
-// its word read.  After x = (x << 16) | w the next slot is w mod 2^P (P <= 12),
-// so every word staged into the ring carries the table entry of that slot.  A
-// round then makes one LDS round trip: lanes that take a word read the word
-// and its entry, the others look up their new slot, in the same wait.
-// `out(i, s, act)` is called by every lane of the wave each round; only lanes
-// with act set hold symbol i.
-template <class Out>
-__device__ bool rans_lit(const uint8_t* body, const Stream& s, uint32_t g, uint32_t P,
-                         const uint32_t* lut, uint16_t* ring, uint32_t* ringe, Out&& out) {
-  const uint32_t lane = lane_id();
-  const uint32_t K = s.K, n = s.n, G = (K + 63) >> 6;
-  const uint32_t k = (g << 6) + lane;
-  const bool lane_ok = k < K;
-  uint32_t woff = 0, nwg = 0;
-  for (uint32_t q = 0; q < G; q++) {
-    const uint32_t c = ld32(body + 4 * K + 4 * q);
-    if (q < g) woff += c;
-    if (q == g) nwg = c;
-  }
-  // unconditional word loads, clamped into the group as in rans_group
-  const uint16_t* W = nwg ? reinterpret_cast<const uint16_t*>(body + 4 * K + 4 * G) + woff
-                          : reinterpret_cast<const uint16_t*>(body);
-  const uint32_t lastw = nwg ? nwg - 1 : 0;
-  auto ldw = [&](uint32_t idx) -> uint32_t { return (uint32_t)W[min(idx, lastw)]; };
-  const uint32_t mask = (1u << P) - 1;
-  uint32_t x = lane_ok ? ld32(body + 4 * k) : kL;
-  bool ok = x >= kL && woff + nwg <= s.nw;
-  // ring of two 128-word slices as in rans_group; slice s+2 waits in pa, pb
-  {
-    uint32_t a[4];
-#pragma unroll
-    for (uint32_t q = 0; q < 4; q++) a[q] = ldw(64 * q + lane);
-#pragma unroll
-    for (uint32_t q = 0; q < 4; q++) {
-      ring[64 * q + lane] = (uint16_t)a[q];
-      ringe[64 * q + lane] = lut[a[q] & mask];
-    }
-  }
-  uint32_t pa = ldw(256 + lane), pb = ldw(320 + lane);
-  uint32_t e = lut[x & mask];
-  uint32_t pos = 0;
-  const uint32_t full = n / K, extra = n - full * K;
-  uint32_t i = k * full + min(k, extra);
-  // One round.  Both reads are issued by every lane (a lane without a word
-  // reads a word it ignores; a lane with one takes its entry from the ring
-  // instead of the table), then the symbol's tile store, so the next round
-  // waits for the reads alone.
-  auto round = [&](bool act) {
-    const uint32_t xd = __umul24((e >> 8) & 0xFFFu, x >> P) + (e >> 20);
-    const uint32_t sym = e & 0xFFu;
-    if (act) x = xd;
-    const bool need = act && x < kL;
-    const uint64_t bal = __ballot(need);
-    const uint32_t q = (pos + mbcnt(bal)) & 255;
-    const uint32_t w = ring[q];
-    e = need ? ringe[q] : lut[x & mask];
-    out(i, sym, act);
-    i += 1;
-    x = need ? (x << 16) | w : x;
-    if (bal) {
-      const uint32_t s0 = pos >> 7;
-      pos += (uint32_t)__popcll(bal);
-      if ((pos >> 7) != s0) {          // entered slice s0+1: stage s0+2, fetch s0+3
-        __builtin_amdgcn_wave_barrier();   // after every lane's read of slice s0
-        const uint32_t ea = lut[pa & mask], eb = lut[pb & mask];
-        const uint32_t d = ((s0 & 1) << 7) + lane;
-        ring[d] = (uint16_t)pa;
-        ring[d + 64] = (uint16_t)pb;
-        ringe[d] = ea;
-        ringe[d + 64] = eb;
-        const uint32_t b3 = (s0 + 3) << 7;
-        pa = ldw(b3 + lane);
-        pb = ldw(b3 + 64 + lane);
-      }
-    }
-  };
-  if ((g << 6) + 64 <= K) {
-    for (uint32_t r = 0; r < full; r++) round(true);   // every lane of the group decodes
-  } else {
-    for (uint32_t r = 0; r < full; r++) round(lane_ok);
-  }
-  if (extra) round(lane_ok && k < extra);
-  ok = ok && (!lane_ok || x == kL) && pos == nwg;
-  return __ballot(!ok) == 0;
-}
-
-// Source byte at absolute position a (an earlier block): direct mode reads the
-// whole-file output; request mode goes through the per-block address table.
-__device__ __forceinline__ uint32_t src_byte(const DevArgs& A, uint64_t a, bool& bad) {
-  if (!A.addr) return A.out[a];
-  const uint64_t base = A.addr[a >> A.bl];
-  if (!base) { bad = true; return 0; }
-  return reinterpret_cast<const uint8_t*>(base)[a & ((1ull << A.bl) - 1)];
-}
-
-// Block-wide exclusive scan of v; *total receives the sum.
-__device__ uint32_t block_scan(Smem& S, uint32_t v, uint32_t* total) {
-  const uint32_t t = threadIdx.x, lane = lane_id(), wv = t >> 6;
-  uint32_t incl = v;
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t y = __shfl_up(incl, d, 64);
-    if (lane >= (uint32_t)d) incl += y;
-  }
-  if (lane == 63) S.scan[wv] = incl;
-  __syncthreads();
-  uint32_t base = 0, tot = 0;
-  for (int q = 0; q < kWaves; q++) {
-    const uint32_t s = S.scan[q];
-    if (q < (int)wv) base += s;
-    tot += s;
-  }
-  __syncthreads();
-  *total = tot;
-  return base + incl - v;
-}
-
-// Small-stream symbol lookup: binary search of slot u in a 257-entry
-// cumulative table; returns symbol | f << 8 | (u - c_s) << 20.
-__device__ __forceinline__ uint32_t search_sym(const uint16_t* cum, uint32_t u) {
-  uint32_t lo = 0;
-#pragma unroll
-  for (uint32_t step = 128; step; step >>= 1)
-    if (cum[lo + step] <= u) lo += step;
-  return lo;
 }
 
 // Symbol owning slot u of a short stream, packed like a literal LUT entry.
@@ -362,10 +199,297 @@ __device__ __forceinline__ uint32_t bucket_sym(const uint16_t* cum, const uint8_
   return s | (((c1 - c0) & 0xFFFu) << 8) | ((u - c0) << 20);
 }
 
+// Decode a short rANS stream (one group of K <= 64 lanes) with one wave.  The
+// record lies in the LDS copy `body`, so words are read from there directly.
+// Lane k decodes the run of consecutive symbols starting at k*R + min(k, e),
+// R = n / K, e = n mod K (container lane layout); round r decodes symbol r of
+// every run still going, renormalisation words are taken in ascending lane
+// order within a round.  `put.start(i)` positions lane state at symbol i and
+// `put(v)` stores the lane's next symbol.  True if every state ends at 2^16 and
+// every word of the group was read.
+template <class Put>
+__device__ bool short_rans(const uint8_t* body, const Stream& s, uint32_t P, const uint16_t* cum,
+                           const uint8_t* bkt, uint32_t bs, Put& put) {
+  const uint32_t lane = lane_id();
+  const uint32_t K = s.K, n = s.n;
+  const bool lane_ok = lane < K;
+  const uint32_t nwg = uni(*reinterpret_cast<const uint32_t*>(body + 4 * K));
+  const uint16_t* W = reinterpret_cast<const uint16_t*>(body + 4 * K + 4);
+  const uint32_t lastw = nwg ? nwg - 1 : 0;
+  uint32_t x = lane_ok ? *reinterpret_cast<const uint32_t*>(body + 4 * lane) : kL;
+  bool ok = x >= kL && nwg == s.nw;
+  const uint32_t R = n / K, e = n - R * K;
+  put.start(lane * R + min(lane, e));
+  const uint32_t mask = (1u << P) - 1;
+  uint32_t pos = 0;
+  auto round = [&](bool act) {
+    if (act) {
+      const uint32_t en = bucket_sym(cum, bkt, bs, x & mask);
+      x = __umul24((en >> 8) & 0xFFFu, x >> P) + (en >> 20);
+      put(en & 0xFFu);
+    }
+    const bool need = act && x < kL;
+    const uint64_t bal = __ballot(need);
+    if (need) x = (x << 16) | (uint32_t)W[min(pos + mbcnt(bal), lastw)];
+    pos += (uint32_t)__popcll(bal);
+  };
+  for (uint32_t r = 0; r < R; r++) round(lane_ok);
+  if (e) round(lane_ok && lane < e);
+  ok = ok && (!lane_ok || x == kL) && pos == nwg;
+  return __ballot(!ok) == 0;
+}
+
+// The first kPreSlices 128-word slices of a literal group, its lanes' initial
+// states and its word range, loaded right after the stream headers are parsed
+// so that their HBM latency is spent on stages 1 and 2.  Word loads are
+// clamped into the group (a group without words reads the first state
+// instead), so every load stays inside the record; a corrupt stream that
+// consumes more words than the group holds fails pos == nwg.
+constexpr uint32_t kPreSlices = 6;
+struct LitPre {
+  uint32_t w[2 * kPreSlices];   // w[2 s + h] = word 128 s + 64 h + lane
+  uint32_t x, woff, nwg;
+};
+
+__device__ __forceinline__ const uint16_t* lit_words(const uint8_t* body, uint32_t K, const LitPre& L) {
+  const uint32_t G = (K + 63) >> 6;
+  return L.nwg ? reinterpret_cast<const uint16_t*>(body + 4 * K + 4 * G) + L.woff
+               : reinterpret_cast<const uint16_t*>(body);
+}
+
+// body: the record body in HBM; cnt: its group word counts (LDS copy or HBM)
+__device__ __forceinline__ void lit_prefetch(const uint8_t* body, const uint8_t* cnt, uint32_t K,
+                                             uint32_t g, LitPre& L) {
+  const uint32_t lane = lane_id(), G = (K + 63) >> 6, k = (g << 6) + lane;
+  L.woff = 0;
+  L.nwg = 0;
+  for (uint32_t q = 0; q < G; q++) {
+    const uint32_t c = uni(ld32(cnt + 4 * q));
+    if (q < g) L.woff += c;
+    if (q == g) L.nwg = c;
+  }
+  const uint16_t* W = lit_words(body, K, L);
+  const uint32_t lastw = L.nwg ? L.nwg - 1 : 0;
+#pragma unroll
+  for (uint32_t i = 0; i < 2 * kPreSlices; i++) L.w[i] = (uint32_t)W[min(64 * i + lane, lastw)];
+  L.x = k < K ? ld32(body + 4 * k) : kL;
+}
+
+// Literal stream, one 64-lane group g of K lanes, every lane active for R
+// rounds (a full group) or under `act` masks (FULL false).  Same symbols,
+// words and checks as short_rans; the group's 16-bit words are staged from HBM
+// through the wave's LDS ring (two 128-word slices, the next two slices in
+// registers), and every staged word carries the table entry of the slot it
+// starts (after x = (x << 16) | w the next slot is w mod 2^P), so a round
+// makes one LDS round trip: renormalising lanes read word and entry, the
+// others look up their new slot.  Each symbol goes straight to its tile
+// position tp; when tp reaches the end of the lane's current literal run
+// (tpend) the lane moves to the next sequence that has literals.
+template <uint32_t P, bool FULL>
+__device__ bool lit_group(const uint8_t* body, uint32_t K, uint32_t n, uint32_t nw_total, uint32_t g,
+                          Smem& S, uint32_t wv, uint32_t ns, const LitPre& L) {
+  const uint32_t lane = lane_id();
+  const uint32_t k = (g << 6) + lane;
+  const bool lane_ok = k < K;
+  const uint32_t nwg = L.nwg;
+  const uint16_t* W = lit_words(body, K, L);
+  const uint32_t lastw = nwg ? nwg - 1 : 0;
+  auto ldw = [&](uint32_t idx) -> uint32_t { return (uint32_t)W[min(idx, lastw)]; };
+  constexpr uint32_t mask = (1u << P) - 1;
+  uint16_t* ring = S.ring[wv];
+  uint32_t* ringe = S.ringe[wv];
+  uint32_t x = L.x;
+  bool ok = x >= kL && L.woff + nwg <= nw_total;
+  // slices 0 and 1 into the ring, slices 2..5 wait in registers
+  {
+    uint32_t en[4];
+#pragma unroll
+    for (uint32_t q = 0; q < 4; q++) en[q] = S.lut[L.w[q] & mask];
+#pragma unroll
+    for (uint32_t q = 0; q < 4; q++) {
+      ring[64 * q + lane] = (uint16_t)L.w[q];
+      ringe[64 * q + lane] = en[q];
+    }
+  }
+  uint32_t rq[2 * kPreSlices - 4];
+#pragma unroll
+  for (uint32_t q = 0; q < 2 * kPreSlices - 4; q++) rq[q] = L.w[4 + q];
+  uint32_t e = S.lut[x & mask];
+  uint32_t pos = 0;
+  const uint32_t R = n / K, ex = n - R * K;
+  // the lane's first literal i0 lies in sequence j: lit[j] <= i0 < lit[j+1]
+  const uint32_t i0 = min(k * R + min(k, ex), n ? n - 1 : 0);
+  uint32_t j = 0;
+  {
+    uint32_t lo = 0, hi = ns - 1;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (S.lit[mid] <= i0) lo = mid; else hi = mid - 1;
+    }
+    j = lo;
+  }
+  uint32_t tp = i0 - S.lit[j] + S.out[j];
+  uint32_t tpend = S.out[j] + (uint32_t)S.lit[j + 1] - S.lit[j];
+  // literal runs of the next three sequences in registers (start, end in the
+  // tile), so that moving to the next run reads no LDS; jq = last queued one
+  uint32_t q1, e1, q2, e2, q3, e3, jq = min(j + 3, ns - 1);
+  {
+    const uint32_t j1 = min(j + 1, ns - 1), j2 = min(j + 2, ns - 1), j3 = jq;
+    q1 = S.out[j1]; e1 = q1 + (uint32_t)S.lit[j1 + 1] - S.lit[j1];
+    q2 = S.out[j2]; e2 = q2 + (uint32_t)S.lit[j2 + 1] - S.lit[j2];
+    q3 = S.out[j3]; e3 = q3 + (uint32_t)S.lit[j3 + 1] - S.lit[j3];
+  }
+  auto round = [&](bool act) {
+    if (act) {
+      S.tile[tp] = (uint8_t)e;
+      x = __umul24((e >> 8) & 0xFFFu, x >> P) + (e >> 20);
+      tp++;
+    }
+    const bool need = act && x < kL;
+    const uint64_t bal = __ballot(need);
+    const uint32_t q = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)bal, pos)) & 255u;
+    const uint32_t w = ring[q];
+    e = need ? ringe[q] : S.lut[x & mask];
+    x = need ? (x << 16) | w : x;
+    if (bal) {
+      const uint32_t s0 = pos >> 7;
+      pos += (uint32_t)__popcll(bal);
+      if ((pos >> 7) != s0) {            // entered slice s0+1: stage s0+2, fetch s0+kPreSlices
+        __builtin_amdgcn_wave_barrier(); // after every lane's read of slice s0
+        const uint64_t c0_ = CLK_NOW();
+        const uint32_t ea = S.lut[rq[0] & mask], eb = S.lut[rq[1] & mask];
+        const uint32_t d = ((s0 & 1) << 7) + lane;
+        ring[d] = (uint16_t)rq[0];
+        ring[d + 64] = (uint16_t)rq[1];
+        ringe[d] = ea;
+        ringe[d + 64] = eb;
+        CLK_ADD(S, 13, CLK_NOW() - c0_);
+        CLK_ADD(S, 14, 1);
+#pragma unroll
+        for (uint32_t q = 0; q + 2 < 2 * kPreSlices - 4; q++) rq[q] = rq[q + 2];
+        const uint32_t b3 = (s0 + kPreSlices) << 7;
+        rq[2 * kPreSlices - 6] = ldw(b3 + lane);
+        rq[2 * kPreSlices - 5] = ldw(b3 + 64 + lane);
+      }
+    }
+    // end of the lane's literal run in this sequence: the next sequence
+    // with literals (every literal index below n_lit has one), from the
+    // register queue while it lasts, else from the tables
+    if (act && tp == tpend) {
+      for (uint32_t hop = 0; hop < 3 && tp == tpend; hop++) {
+        tp = q1; tpend = e1;
+        q1 = q2; e1 = e2;
+        q2 = q3; e2 = e3;
+        q3 = e3;                          // empty run: exhausts the queue
+      }
+      if (tp == tpend) {
+        uint32_t nj = jq + 1;
+        while (nj + 1 < ns && S.lit[nj + 1] == S.lit[nj]) nj++;
+        jq = min(nj, ns - 1);
+        tp = S.out[jq];
+        tpend = tp + (uint32_t)S.lit[jq + 1] - S.lit[jq];
+        q1 = q2 = q3 = e1 = e2 = e3 = tpend;
+      }
+    }
+  };
+  if (FULL) {
+    for (uint32_t r = 0; r < R; r++) round(true);
+  } else {
+    for (uint32_t r = 0; r < R; r++) round(lane_ok);
+  }
+  if (ex) round(lane_ok && k < ex);
+  ok = ok && (!lane_ok || x == kL) && pos == nwg;
+  return __ballot(!ok) == 0;
+}
+
+template <uint32_t P>
+__device__ bool lit_group_p(const uint8_t* body, uint32_t K, uint32_t n, uint32_t nw, uint32_t g,
+                            Smem& S, uint32_t wv, uint32_t ns, const LitPre& L) {
+  if ((g << 6) + 64 <= K) return lit_group<P, true>(body, K, n, nw, g, S, wv, ns, L);
+  return lit_group<P, false>(body, K, n, nw, g, S, wv, ns, L);
+}
+
+// Source byte at absolute position a (an earlier block): direct mode reads the
+// whole-file output; request mode goes through the per-block address table.
+__device__ __forceinline__ uint32_t src_byte(const DevArgs& A, uint64_t a, bool& bad) {
+  if (!A.addr) return A.out[a];
+  const uint64_t base = A.addr[a >> A.bl];
+  if (!base) { bad = true; return 0; }
+  return reinterpret_cast<const uint8_t*>(base)[a & ((1ull << A.bl) - 1)];
+}
+
+// Inclusive scan over the 64 lanes of a wave with DPP moves (no LDS): shifts
+// by 1, 2, 4 and 8 inside each 16-lane row, then the last lane of row 0 is
+// added to row 1 and of row 2 to row 3 (row_bcast:15), then lane 31 to rows
+// 2 and 3 (row_bcast:31).  Lanes whose DPP source is outside the row read 0.
+__device__ __forceinline__ uint32_t wave_scan(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);   // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);   // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);   // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);   // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);   // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);   // row_bcast:31
+  return v;
+}
+
+// Block-wide exclusive scans of three counts at once; tot[] receives the sums.
+__device__ void block_scan3(Smem& S, const uint32_t v[3], uint32_t pre[3], uint32_t tot[3]) {
+  const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
+  uint32_t incl[3];
+#pragma unroll
+  for (int f = 0; f < 3; f++) {
+    incl[f] = wave_scan(v[f]);
+    if (lane == 63) S.scan[f][wv] = incl[f];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int f = 0; f < 3; f++) {
+    uint32_t base = 0, all = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < kWaves; q++) {
+      const uint32_t w = S.scan[f][q];
+      if (q < wv) base += w;
+      all += w;
+    }
+    pre[f] = base + incl[f] - v[f];
+    tot[f] = all;
+  }
+  __syncthreads();
+}
+
+// Small-stream symbol lookup: binary search of slot u in a 257-entry
+// cumulative table.
+__device__ __forceinline__ uint32_t search_sym(const uint16_t* cum, uint32_t u) {
+  uint32_t lo = 0;
+#pragma unroll
+  for (uint32_t step = 128; step; step >>= 1)
+    if (cum[lo + step] <= u) lo += step;
+  return lo;
+}
+
+// Writes the decoded values of a short stream: symbol i is byte plane i / ns
+// of value i mod ns (values stored byte-plane major); a lane's symbols are
+// consecutive, so its (plane, index) pair advances by one each call.
+struct PutPlanes {
+  uint8_t* lo;      // planes 0..lo_planes-1: byte `plane` of the value at lo + stride * idx
+  uint8_t* hi;      // plane 4 (offsets only): hi[idx]
+  uint32_t stride, ns, idx, plane;
+  __device__ void start(uint32_t i) {
+    plane = i / ns;
+    idx = i - plane * ns;
+  }
+  __device__ void operator()(uint32_t v) {
+    if (plane < 4) lo[stride * idx + min(plane, stride - 1)] = (uint8_t)v;
+    else hi[idx] = (uint8_t)v;
+    if (++idx == ns) { idx = 0; plane++; }
+  }
+};
+
 // Decode block b into the LDS tile and store it.  Every loop below is bounded
 // by values read from global memory (directory, stream headers).
 __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
-  const uint32_t t = threadIdx.x, wv = t >> 6, lane = lane_id();
+  const uint32_t t = threadIdx.x, wv = uni(t >> 6), lane = lane_id();
   const uint64_t B = 1ull << A.bl;
   const uint64_t sb = (uint64_t)b << A.bl;
   const uint32_t blen = (uint32_t)((sb + B <= A.n) ? B : A.n - sb);
@@ -373,11 +497,12 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
   const uint64_t poff = ld64(de);
   const uint32_t plen = ld32(de + 8), ns = ld32(de + 12), nlit = ld32(de + 16);
   const uint8_t* pay = A.arc + A.off_payload + poff;
+  CLK_START(S);
 
-  // The first min(plen, 16 KiB) payload bytes are copied into the tile (free
-  // until stage 3) with one round of 16-byte loads: the stream headers and
-  // the short streams CMD, MLEN, OFF (at most about 9.3 KB with their headers
-  // for 1025 sequences) are read from there; the literal stream from HBM.
+  // ---- stage 0: the first min(plen, 16 KiB) payload bytes into the tile
+  // (free until stage 3) with one round of 16-byte loads: the stream headers
+  // and the short streams (at most about 9.3 KB with their headers for 1025
+  // sequences) are read from there; the literal stream from HBM.
   const uint32_t hlen = min(plen, kB);
   {
     const uint4* src4 = reinterpret_cast<const uint4*>(pay);
@@ -385,7 +510,9 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
     for (uint32_t c = t; c < (hlen >> 4); c += kWG) dst4[c] = src4[c];
     if (t < (hlen & 15u)) S.tile[(hlen & ~15u) + t] = pay[(hlen & ~15u) + t];
   }
+  if (t == 0) { S.err = 0; S.nin = 0; S.next = 0; }
   __syncthreads();
+  CLK_MARK(S, 0);
   const uint8_t* hp = S.tile;
 
   // stream records: CMD, MLEN, OFF, LIT (every thread parses the same bytes)
@@ -400,71 +527,107 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
     if (t == 0) latch(A.ctl, kStCorrupt);
     return;
   }
+  // literal group of this wave (K <= 256: at most one per wave), fetched ahead
+  const uint32_t Glit = sl.mode == kModeRans ? (sl.K + 63) >> 6 : 0u;
+  LitPre lp;
+  if (wv < Glit) {
+    const uint32_t co = sl.body + 4 * sl.K;     // group word counts: from the copy when inside it
+    lit_prefetch(pay + sl.body, co + 4 * Glit <= hlen ? hp + co : pay + co, sl.K, wv, lp);
+  }
+  CLK_MARK(S, 1);
 
   // ---- stage 1: CMD -> lit[] (LL), MLEN -> out[] (ML), OFF -> oflo/ofhi
-  for (uint32_t j = t; j < ns; j += kWG) { S.oflo[j] = 0; S.ofhi[j] = 0; }
-  if (t == 0) { S.err = 0; S.nint = 0; }
-  __syncthreads();
   if (wv < 3) {
     const Stream& s = wv == 0 ? sc : (wv == 1 ? sm : so);
-    const uint16_t* cum = S.cum[wv];
-    const uint32_t bs = A.P[1 + wv] > 8 ? A.P[1 + wv] - 8 : 0u;
-    uint8_t* dst8 = wv == 0 ? reinterpret_cast<uint8_t*>(S.lit) : reinterpret_cast<uint8_t*>(S.out);
-    auto put = [&](uint32_t i, uint32_t v) {
-      uint32_t plane = 0, idx = i;
-      while (idx >= ns && plane < 7) { idx -= ns; plane++; }
-      if (wv < 2) {
-        dst8[2 * idx + plane] = (uint8_t)v;
-      } else if (plane < 4) {
-        reinterpret_cast<uint8_t*>(S.oflo)[4 * idx + plane] = (uint8_t)v;
-      } else {
-        S.ofhi[idx] = (uint8_t)v;
-      }
-    };
+    PutPlanes put;
+    put.ns = ns;
+    if (wv < 2) {
+      put.lo = wv == 0 ? reinterpret_cast<uint8_t*>(S.lit) : reinterpret_cast<uint8_t*>(S.out);
+      put.hi = put.lo;
+      put.stride = 2;
+    } else {
+      put.lo = reinterpret_cast<uint8_t*>(S.oflo);
+      put.hi = S.ofhi;
+      put.stride = 4;
+    }
+    // offsets narrower than 5 bytes: clear the planes the stream does not hold
+    if (wv == 2) {
+      for (uint32_t j = lane; j < ns; j += 64) { S.oflo[j] = 0; S.ofhi[j] = 0; }
+      __builtin_amdgcn_wave_barrier();
+    }
     bool okw = true;
     if (s.mode == kModeRans) {
-      okw = rans_group(hp + s.body, s, 0, A.P[1 + wv], S.ring[wv],
-                       [&](uint32_t u) { return bucket_sym(cum, S.bkt[wv], bs, u); }, put);
-    } else if (s.mode == kModeRaw) {
+      const uint32_t P = A.P[1 + wv];
+      const uint32_t bs = P > 8 ? P - 8 : 0u;
+      okw = short_rans(hp + s.body, s, P, S.cum[wv], S.bkt[wv], bs, put);
+    } else if (s.mode == kModeRaw || s.mode == kModeConst) {
       const uint8_t* src = hp + s.body;
-      for (uint32_t i = lane; i < s.n; i += 64) put(i, src[i]);
-    } else if (s.mode == kModeConst) {
-      for (uint32_t i = lane; i < s.n; i += 64) put(i, s.csym);
+      for (uint32_t i = lane; i < s.n; i += 64) {
+        put.start(i);
+        put(s.mode == kModeRaw ? (uint32_t)src[i] : s.csym);
+      }
     }
     if (!okw && lane == 0) S.err = 1;
   }
   __syncthreads();
+  CLK_MARK(S, 2);
 
-  // ---- stage 2: command placement; in-place exclusive scans of LL and LL+ML
+  // ---- stage 2: command placement.  One block scan of (LL, LL + ML,
+  // in-block match) counts gives literal and output positions and the order
+  // of the in-block matches; the block's sequence invariants are checked.
+  // Values are u16 and ns <= 1025, so no sum reaches 2^32.
   {
-    const uint32_t per = (ns + kWG - 1) / kWG;
+    const uint32_t per = (ns + kWG - 1) / kWG;   // <= 5
     const uint32_t j0 = min(ns, t * per), j1 = min(ns, j0 + per);
     uint32_t ll[5], ml[5];
-    uint32_t sl_ = 0, so_ = 0;
-    for (uint32_t j = j0, q = 0; j < j1; j++, q++) {
-      ll[q] = S.lit[j];
-      ml[q] = S.out[j];
-      sl_ += ll[q];
-      so_ += ll[q] + ml[q];
+    uint32_t v[3] = {0, 0, 0};
+    bool bad = false;
+#pragma unroll
+    for (uint32_t q = 0; q < 5; q++) {
+      const uint32_t j = j0 + q;
+      ll[q] = j < j1 ? S.lit[j] : 0u;
+      ml[q] = j < j1 ? S.out[j] : 0u;
+      uint32_t inb = 0;
+      if (j < j1 && ml[q]) {
+        const uint64_t of = (uint64_t)S.oflo[j] | ((uint64_t)S.ofhi[j] << 32);
+        inb = of + ml[q] > sb ? 1u : 0u;
+      }
+      v[0] += ll[q];
+      v[1] += ll[q] + ml[q];
+      v[2] += inb;
     }
-    uint32_t tl, to;
-    uint32_t pl = block_scan(S, sl_, &tl);
-    uint32_t po = block_scan(S, so_, &to);
-    bool bad = tl != nlit || to != blen;
-    for (uint32_t j = j0, q = 0; j < j1; j++, q++) {
-      S.lit[j] = (uint16_t)pl;
-      S.out[j] = (uint16_t)po;
-      const uint64_t of = (uint64_t)S.oflo[j] | ((uint64_t)S.ofhi[j] << 32);
-      if (ml[q] == 0) bad |= (j != ns - 1) || of != 0;
-      else bad |= ml[q] < A.m || of >= sb + po + ll[q];
-      // matches with a source wholly in earlier blocks, listed in any order
-      if (ml[q] && of + ml[q] <= sb) S.intl[atomicAdd(&S.nint, 1u)] = (uint16_t)j;
-      pl += ll[q];
-      po += ll[q] + ml[q];
+    uint32_t pre[3], tot[3];
+    block_scan3(S, v, pre, tot);
+    const uint32_t tl = tot[0], to = tot[1];
+    bad |= tl != nlit || to != blen;
+    uint32_t pl = pre[0], po = pre[1];
+    uint32_t pin = pre[2];
+#pragma unroll
+    for (uint32_t q = 0; q < 5; q++) {
+      const uint32_t j = j0 + q;
+      if (j < j1) {
+        S.lit[j] = (uint16_t)pl;
+        S.out[j] = (uint16_t)po;
+        const uint64_t of = (uint64_t)S.oflo[j] | ((uint64_t)S.ofhi[j] << 32);
+        if (ml[q] == 0) {
+          bad |= (j != ns - 1) || of != 0;
+        } else {
+          bad |= ml[q] < A.m || of >= sb + po + ll[q];
+          if (of + ml[q] <= sb) {
+            S.lst[atomicAdd(&S.next, 1u)] = (uint16_t)j;   // from earlier blocks, any order
+          } else {
+            S.lst[kMaxSeq - 1 - pin] = (uint16_t)j;        // in-block, in sequence order
+            pin++;
+          }
+        }
+        pl += ll[q];
+        po += ll[q] + ml[q];
+      }
     }
     if (t == 0) {
       S.lit[ns] = (uint16_t)min(tl, 65535u);
       S.out[ns] = (uint16_t)min(to, 65535u);
+      S.nin = tot[2];
     }
     if (bad) S.err = 1;
   }
@@ -473,82 +636,109 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
     if (t == 0) latch(A.ctl, kStCorrupt);
     return;
   }
+  CLK_MARK(S, 3);
 
   // ---- stage 3: literals straight to their tile positions; external matches
   {
     bool bad = false;
-    // per-lane sequence cursor: literal i belongs to sequence j, the last one
-    // with lit[j] <= i; its output position is i + (out[j] - lit[j])
-    uint32_t j = 0, nxt = S.lit[1], dlt = S.out[0] - S.lit[0];
-    auto seek = [&](uint32_t i) {              // binary search over lit[0..ns-1]
-      uint32_t lo = 0, hi = ns ? ns - 1 : 0;
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi + 1) >> 1;
-        if (S.lit[mid] <= i) lo = mid; else hi = mid - 1;
+    const uint32_t nx = min(S.next, ns), slot = lane >> 3, sub = lane & 7;
+    // Matches with a source wholly in earlier blocks.  In whole-file mode the
+    // first eight are started before the literal decode, two per wave (one
+    // per half-wave): each lane loads two aligned source words covering eight
+    // bytes of the match's first 256, so the HBM latency is spent decoding;
+    // the bytes are stored after it.  The rest are copied eight per wave at a
+    // time, one per 8-lane slot, each lane every eighth byte, all loads in
+    // flight before the stores.
+    const bool early = A.addr == nullptr;
+    const uint32_t half = lane >> 5, hsub = lane & 31;
+    uint32_t pM = 0, pd0 = 0, pw0 = 0, pw1 = 0;
+    uint64_t pof = 0, pa = 0;
+    if (early) {
+      const uint32_t e = 2 * wv + half;
+      const uint32_t q = e < nx ? min((uint32_t)S.lst[e], ns - 1) : 0u;
+      const uint32_t L = (uint32_t)S.lit[q + 1] - S.lit[q];
+      pM = e < nx ? (uint32_t)S.out[q + 1] - S.out[q] - L : 0u;
+      pof = (uint64_t)S.oflo[q] | ((uint64_t)S.ofhi[q] << 32);
+      pd0 = S.out[q] + L;
+      // words [pa, pa + 8) with pa = (of & ~3) + 8 * hsub cover the bytes
+      // k < 256 - (of & 3) of the match; the last word may reach up to 3 bytes
+      // past the match, still inside the output (the source ends at or
+      // before this block's start)
+      pa = (pof & ~3ull) + 8ull * hsub;
+      const uint32_t* w = reinterpret_cast<const uint32_t*>(A.out + pa);
+      const uint64_t lim = pof + min(pM, 256u - (uint32_t)(pof & 3));
+      pw0 = pa < lim ? w[0] : 0u;
+      pw1 = pa + 4 < lim ? w[1] : 0u;
+    }
+    if (wv < Glit) {
+      const uint32_t g = wv;
+      bool okg;
+      switch (A.P[kLit]) {
+        case 8: okg = lit_group_p<8>(pay + sl.body, sl.K, sl.n, sl.nw, g, S, wv, ns, lp); break;
+        case 9: okg = lit_group_p<9>(pay + sl.body, sl.K, sl.n, sl.nw, g, S, wv, ns, lp); break;
+        case 10: okg = lit_group_p<10>(pay + sl.body, sl.K, sl.n, sl.nw, g, S, wv, ns, lp); break;
+        case 11: okg = lit_group_p<11>(pay + sl.body, sl.K, sl.n, sl.nw, g, S, wv, ns, lp); break;
+        default: okg = lit_group_p<12>(pay + sl.body, sl.K, sl.n, sl.nw, g, S, wv, ns, lp); break;
       }
-      j = lo;
-      nxt = S.lit[j + 1];
-      dlt = (uint32_t)S.out[j] - (uint32_t)S.lit[j];
-    };
-    // called by every lane of the wave; lanes with act false store nothing
-    auto place = [&](uint32_t i, uint32_t v, bool act) {
-      if (__ballot(act && i >= nxt && j + 1 < ns)) {   // some lane entered a later sequence
-        while (act && i >= nxt && j + 1 < ns) {
-          j++;
-          nxt = S.lit[j + 1];
-          dlt = (uint32_t)S.out[j] - (uint32_t)S.lit[j];
+      if (!okg) bad = true;
+    } else if (sl.mode == kModeRaw || sl.mode == kModeConst) {
+      // one thread per literal: the sequence by binary search
+      const uint8_t* src = pay + sl.body;
+      for (uint32_t i = t; i < sl.n; i += kWG) {
+        uint32_t lo = 0, hi = ns - 1;
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi + 1) >> 1;
+          if (S.lit[mid] <= i) lo = mid; else hi = mid - 1;
+        }
+        const uint32_t p = i - S.lit[lo] + S.out[lo];
+        S.tile[min(p, kB - 1)] = sl.mode == kModeRaw ? src[i] : (uint8_t)sl.csym;
+      }
+    }
+    CLK_MARK(S, 4);
+    if (early) {
+      const uint64_t lim = pof + min(pM, 256u - (uint32_t)(pof & 3));
+#pragma unroll
+      for (uint32_t u = 0; u < 8; u++) {
+        const uint64_t a = pa + u;
+        const uint32_t v = (u < 4 ? pw0 : pw1) >> (8 * (u & 3));
+        if (a >= pof && a < lim) S.tile[pd0 + (uint32_t)(a - pof)] = (uint8_t)v;
+      }
+      for (uint32_t k0 = 256u - (uint32_t)(pof & 3); __ballot(k0 < pM); k0 += 256) {   // the rest
+        uint32_t v[8];
+        const uint8_t* p = A.out + pof + k0 + hsub;
+#pragma unroll
+        for (uint32_t u = 0; u < 8; u++) v[u] = k0 + hsub + 32 * u < pM ? (uint32_t)p[32 * u] : 0u;
+#pragma unroll
+        for (uint32_t u = 0; u < 8; u++) {
+          const uint32_t k = k0 + hsub + 32 * u;
+          if (k < pM && pd0 + k < blen) S.tile[pd0 + k] = (uint8_t)v[u];
         }
       }
-      // i < lit[j+1] and the scans checked in stage 2 put i + dlt below
-      // out[j+1] <= blen; the mask only keeps the store inside the tile
-      if (act) S.tile[(i + dlt) & (kB - 1)] = (uint8_t)v;
-    };
-    if (sl.mode == kModeRans) {
-      const uint32_t G = (sl.K + 63) >> 6, R = sl.n / sl.K, e = sl.n - R * sl.K;
-      for (uint32_t g = wv; g < G; g += kWaves) {
-        const uint32_t k = (g << 6) + lane;   // this lane's run starts at k*R + min(k, e)
-        seek(min(k * R + min(k, e), sl.n - 1));
-        if (!rans_lit(pay + sl.body, sl, g, A.P[kLit], S.lut, S.ring[wv], S.ringe[wv], place)) bad = true;
-      }
-    } else if (sl.mode == kModeRaw) {
-      const uint8_t* src = pay + sl.body;
-      for (uint32_t i0 = 0; i0 < sl.n; i0 += kWG) {
-        const uint32_t i = i0 + t;
-        place(i, i < sl.n ? src[i] : 0u, i < sl.n);
-      }
-    } else if (sl.mode == kModeConst) {
-      for (uint32_t i0 = 0; i0 < sl.n; i0 += kWG) place(i0 + t, sl.csym, i0 + t < sl.n);
     }
-    // matches with a source wholly in earlier blocks (listed in stage 2):
-    // eight per wave at a time, one per 8-lane slot, each lane every eighth
-    // byte, all loads in flight before the stores
-    {
-      const uint32_t nx = min(S.nint, ns), slot = lane >> 3, sub = lane & 7;
-      for (uint32_t g0 = 8 * wv; g0 < nx; g0 += 8 * kWaves) {
-        const uint32_t e = g0 + slot;
-        const uint32_t q = e < nx ? min((uint32_t)S.intl[e], ns - 1) : 0u;
-        const uint32_t L = (uint32_t)S.lit[q + 1] - S.lit[q];
-        const uint32_t M = e < nx ? (uint32_t)S.out[q + 1] - S.out[q] - L : 0u;
-        const uint64_t of = (uint64_t)S.oflo[q] | ((uint64_t)S.ofhi[q] << 32);
-        const uint32_t d0 = S.out[q] + L;
-        for (uint32_t k0 = 0; k0 < M; k0 += 64) {
-          uint32_t v[8];
-          if (!A.addr) {                       // whole-file output: one base, byte offsets
-            const uint8_t* p = A.out + of + k0 + sub;
+    for (uint32_t g0 = 8 * wv + (early ? 2 * kWaves : 0u); g0 < nx; g0 += 8 * kWaves) {
+      const uint32_t e = g0 + slot;
+      const uint32_t q = e < nx ? min((uint32_t)S.lst[e], ns - 1) : 0u;
+      const uint32_t L = (uint32_t)S.lit[q + 1] - S.lit[q];
+      const uint32_t M = e < nx ? (uint32_t)S.out[q + 1] - S.out[q] - L : 0u;
+      const uint64_t of = (uint64_t)S.oflo[q] | ((uint64_t)S.ofhi[q] << 32);
+      const uint32_t d0 = S.out[q] + L;
+      for (uint32_t k0 = 0; __ballot(k0 < M); k0 += 256) {
+        uint32_t v[32];
+        if (!A.addr) {                       // whole-file output: one base, byte offsets
+          const uint8_t* p = A.out + of + k0 + sub;
 #pragma unroll
-            for (uint32_t u = 0; u < 8; u++) v[u] = k0 + sub + 8 * u < M ? (uint32_t)p[8 * u] : 0u;
-          } else {
+          for (uint32_t u = 0; u < 32; u++) v[u] = k0 + sub + 8 * u < M ? (uint32_t)p[8 * u] : 0u;
+        } else {
 #pragma unroll
-            for (uint32_t u = 0; u < 8; u++) {
-              const uint32_t k = k0 + sub + 8 * u;
-              v[u] = k < M ? src_byte(A, of + k, bad) : 0u;
-            }
-          }
-#pragma unroll
-          for (uint32_t u = 0; u < 8; u++) {
+          for (uint32_t u = 0; u < 32; u++) {
             const uint32_t k = k0 + sub + 8 * u;
-            if (k < M && d0 + k < blen) S.tile[d0 + k] = (uint8_t)v[u];
+            v[u] = k < M ? src_byte(A, of + k, bad) : 0u;
           }
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < 32; u++) {
+          const uint32_t k = k0 + sub + 8 * u;
+          if (k < M && d0 + k < blen) S.tile[d0 + k] = (uint8_t)v[u];
         }
       }
     }
@@ -559,44 +749,29 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
     if (t == 0) latch(A.ctl, kStCorrupt);
     return;
   }
+  CLK_MARK(S, 5);
 
   // ---- stage 4: matches whose source touches the block itself.
   // With period d = p - OF, out[p+k] = out[OF + (k mod d)] for every k (the
   // byte-sequential overlap rule unrolled); only the window OF..OF+min(d,M)-1
   // is read and it is final once every earlier match writing into it is done.
-  // 4a: ordered list of these matches (ballot compaction, wave 0);
-  // 4b: per match: destination, length, source (block-relative), period and
-  //     the range of earlier such matches whose destinations its window
-  //     meets (binary searches over the sorted destinations), packed into
-  //     the sequence tables, which are no longer needed;
-  // 4c: matches with an empty range copied by all waves in parallel;
-  // 4d: the others copied by wave 0 in passes, each pass the matches whose
-  //     earlier sources are complete.
-  if (wv == 0) {
-    uint32_t base = 0;
-    for (uint32_t q0 = 0; q0 < ns; q0 += 64) {
-      const uint32_t q = q0 + lane;
-      bool in = false;
-      if (q < ns) {
-        const uint32_t L = (uint32_t)S.lit[q + 1] - S.lit[q];
-        const uint32_t M = (uint32_t)S.out[q + 1] - S.out[q] - L;
-        const uint64_t of = (uint64_t)S.oflo[q] | ((uint64_t)S.ofhi[q] << 32);
-        in = M && of + M > sb;
-      }
-      const uint64_t bal = __ballot(in);
-      if (in) S.intl[base + mbcnt(bal)] = (uint16_t)q;
-      base += (uint32_t)__popcll(bal);
-    }
-    if (lane == 0) S.nint = base;
-  }
-  __syncthreads();
-  const uint32_t cnt = min(S.nint, ns);
-  {
-    // 4b phase 1: per match in registers (at most 5 per thread)
+  // 4a: per match a (sequence order): destination, length, block-relative
+  //     source and period, and the index range of earlier in-block matches
+  //     whose destinations its window meets (two binary searches over the
+  //     sorted, disjoint destinations), packed into the sequence tables;
+  // 4b: wave 0 copies them in passes over 64-entry chunks (every earlier
+  //     chunk complete): a pass takes every pending match whose predecessors
+  //     are done.  Short matches (at most 64 bytes, no overlap with themselves,
+  //     source inside the tile) are copied by their own lane from four-byte
+  //     words; the others by the whole wave, one at a time.
+  const uint32_t cnt = min(S.nin, ns);
+  if (cnt) {
     uint32_t md0[5], mM[5], ms[5], md[5];
     const uint32_t per = (cnt + kWG - 1) / kWG, a0 = min(cnt, t * per), a1 = min(cnt, a0 + per);
-    for (uint32_t a = a0, u = 0; a < a1; a++, u++) {
-      const uint32_t q = min((uint32_t)S.intl[a], ns - 1);
+#pragma unroll
+    for (uint32_t u = 0; u < 5; u++) {
+      const uint32_t a = a0 + u;
+      const uint32_t q = a < a1 ? min((uint32_t)S.lst[kMaxSeq - 1 - a], ns - 1) : 0u;
       const uint32_t L = (uint32_t)S.lit[q + 1] - S.lit[q];
       const uint32_t M = min((uint32_t)S.out[q + 1] - S.out[q] - L, blen);
       const uint32_t d0 = S.out[q] + L;
@@ -604,70 +779,63 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
       const uint64_t dabs = sb + d0;
       md0[u] = d0;
       mM[u] = M;
-      // of >= sb - M here (the source overlaps the block), so the relative
-      // source fits in [-16384, 16384)
+      // of + M > sb here (the source window touches the block) and of < dabs,
+      // so the relative source fits in [-16384, 16384)
       ms[u] = (uint32_t)((int64_t)of - (int64_t)sb + 16384) & 0xFFFFu;
       md[u] = dabs > of ? (uint32_t)min<uint64_t>(dabs - of, 32767) : 1u;
     }
     __syncthreads();
-    for (uint32_t a = a0, u = 0; a < a1; a++, u++) {
-      S.lit[a] = (uint16_t)md0[u];
-      S.out[a] = (uint16_t)mM[u];
+#pragma unroll
+    for (uint32_t u = 0; u < 5; u++) {
+      const uint32_t a = a0 + u;
+      if (a < a1) {
+        S.lit[a] = (uint16_t)md0[u];
+        S.out[a] = (uint16_t)mM[u];
+      }
     }
     __syncthreads();
-    // 4b phase 2: the earlier matches whose destinations meet the window
-    // form an index range [lo, hi) (destinations are sorted and disjoint);
-    // the match is dependent if it is not empty.  The part of the range inside
-    // the match's own 64-entry chunk is kept as bit positions (plo, phi).
-    for (uint32_t a = a0, u = 0; a < a1; a++, u++) {
-      const int32_t s = (int32_t)ms[u] - 16384;
-      const uint32_t w = min(md[u], mM[u]);
-      uint32_t lo = a, hi = a;
-      if (s + (int32_t)w > 0) {
-        const uint32_t ws = s > 0 ? (uint32_t)s : 0u, we = (uint32_t)(s + (int32_t)w);
-        // two searches over [0, a) in lockstep: lo = first earlier match whose
-        // destination ends after ws, hi = first whose destination starts at
-        // or after we (hi >= lo: such a destination also ends after ws)
-        uint32_t l1 = 0, h1 = a, l2 = 0, h2 = a;
-        while (l1 < h1 || l2 < h2) {
-          const uint32_t m1 = (l1 + h1) >> 1, m2 = (l2 + h2) >> 1;
-          const uint32_t e1 = (uint32_t)S.lit[min(m1, a - 1)] + S.out[min(m1, a - 1)];
-          const uint32_t b2 = S.lit[min(m2, a - 1)];
-          if (l1 < h1) { if (e1 > ws) h1 = m1; else l1 = m1 + 1; }
-          if (l2 < h2) { if (b2 >= we) h2 = m2; else l2 = m2 + 1; }
+#pragma unroll
+    for (uint32_t u = 0; u < 5; u++) {
+      const uint32_t a = a0 + u;
+      if (a < a1) {
+        const int32_t s = (int32_t)ms[u] - 16384;
+        const uint32_t w = min(md[u], mM[u]);
+        uint32_t lo = a, hi = a;
+        if (s + (int32_t)w > 0) {
+          const uint32_t ws = s > 0 ? (uint32_t)s : 0u, we = (uint32_t)(s + (int32_t)w);
+          // lo = first earlier match whose destination ends after ws, hi =
+          // first whose destination starts at or after we (hi >= lo)
+          uint32_t l1 = 0, h1 = a, l2 = 0, h2 = a;
+          while (l1 < h1 || l2 < h2) {
+            const uint32_t m1 = (l1 + h1) >> 1, m2 = (l2 + h2) >> 1;
+            const uint32_t e1 = (uint32_t)S.lit[min(m1, a - 1)] + S.out[min(m1, a - 1)];
+            const uint32_t b2 = S.lit[min(m2, a - 1)];
+            if (l1 < h1) { if (e1 > ws) h1 = m1; else l1 = m1 + 1; }
+            if (l2 < h2) { if (b2 >= we) h2 = m2; else l2 = m2 + 1; }
+          }
+          lo = l1;
+          hi = l2;
         }
-        lo = l1;
-        hi = l2;
+        const uint32_t c0 = a & ~63u;
+        const uint32_t plo = max(lo, c0) - c0, phi = max(hi, c0) - c0;   // both <= 63
+        S.lst[a] = (uint16_t)(plo | (phi << 8));
+        S.oflo[a] = ms[u] | (md[u] << 16);
       }
-      const bool dep = lo < hi;
-      const uint32_t c0 = a & ~63u;
-      const uint32_t plo = max(lo, c0) - c0, phi = max(hi, c0) - c0;   // both <= 63
-      S.intl[a] = (uint16_t)(plo | (phi << 8));
-      S.oflo[a] = ms[u] | (md[u] << 16) | (dep ? 0x80000000u : 0u);
     }
   }
   __syncthreads();
-  {
+  CLK_MARK(S, 6);
+  if (wv == 0 && cnt) {
     bool bad = false;
+    // whole-wave copy of in-block match a (any length, period and source)
     auto copy_match = [&](uint32_t a) {
       const uint32_t pk = S.oflo[a];
       const uint32_t d0 = S.lit[a], M = S.out[a];
       const int32_t s = (int32_t)(pk & 0xFFFFu) - 16384;
       const uint32_t d = (pk >> 16) & 0x7FFFu;
-      if (d >= M) {                         // no overlap with itself: a plain copy
-        for (uint32_t k = lane; k < M; k += 64) {
-          if (d0 + k < blen) {
-            const int32_t src = s + (int32_t)k;
-            const uint32_t v = src >= 0 ? (uint32_t)S.tile[(uint32_t)src & (kB - 1)]
-                                        : src_byte(A, sb + (int64_t)src, bad);
-            S.tile[d0 + k] = (uint8_t)v;
-          }
-        }
-        return;
-      }
-      // (c + lane) mod d, kept incrementally (a division only for d < 64)
-      uint32_t r = d >= 64 ? lane : lane % d;
-      const uint32_t r64 = d >= 64 ? 64u : 64u % d;
+      // (k mod d) kept incrementally (a division only for d < 64)
+      uint32_t r = d >= M ? lane : (d >= 64 ? lane : lane % d);
+      const uint32_t r64 = d >= M ? 64u : (d >= 64 ? 64u : 64u % d);
       for (uint32_t c = 0; c < M; c += 64) {
         const uint32_t k = c + lane;
         if (k < M && d0 + k < blen) {
@@ -677,98 +845,69 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
           S.tile[d0 + k] = (uint8_t)v;
         }
         r += r64;
-        if (r >= d) r -= d;
+        if (d < M && r >= d) r -= d;
       }
     };
-    // 4c: matches with an empty range, all waves: a wave tests 64 of its
-    // entries (a = wv + 4 l) at once, then copies the ones that qualify
-    for (uint32_t a0 = wv; a0 < cnt; a0 += kWaves * 64) {
-      const uint32_t a = a0 + kWaves * lane;
-      uint64_t m = __ballot(a < cnt && !(S.oflo[min(a, cnt - 1)] & 0x80000000u));
-      while (m) {                              // wave-uniform
-        const uint32_t l = (uint32_t)__builtin_ctzll(m);
-        m &= m - 1;
-        copy_match(a0 + kWaves * l);
-      }
-    }
-    __syncthreads();
-    // 4d: dependent matches, wave 0, in passes over 64-entry chunks (every
-    // earlier chunk is complete).  Lane l holds the predecessor bits of entry
-    // c0 + l; a pass takes every pending match whose in-chunk predecessors
-    // are all done, which includes the lowest pending one, so a chunk takes
-    // at most 64 passes.  Matches of one pass do not read each other's
-    // destinations.  The pass's matches are listed in LDS and copied eight at
-    // a time, one per 8-lane slot, each lane every eighth byte (loads, then
-    // stores); a match longer than 64 bytes or shorter than its period is
-    // copied by the whole wave.  LDS operations of one wave are performed in
-    // order, so a pass sees every earlier pass.
-    if (wv == 0) {
-      const uint32_t slot = lane >> 3, sub = lane & 7;
-      for (uint32_t c0 = 0; c0 < cnt; c0 += 64) {
-        const uint32_t a = c0 + lane;
-        const bool have = a < cnt;
-        const uint32_t rng = have ? (uint32_t)S.intl[a] : 0u;
-        const uint32_t plo = rng & 63u, phi = (rng >> 8) & 63u;
-        const uint64_t needm = phi > plo ? (1ull << phi) - (1ull << plo) : 0ull;
-        const uint32_t mpk = have ? S.oflo[a] : 0u;
-        const uint32_t mdl = have ? (uint32_t)S.lit[a] | ((uint32_t)S.out[a] << 16) : 0u;
-        bool pending = have && (mpk & 0x80000000u);
-        uint64_t done = ~__ballot(pending);
-        for (uint32_t pass = 0; pass <= 64; pass++) {
-          const bool ready = pending && (needm & ~done) == 0;
-          const uint64_t m = __ballot(ready);
-          if (!m) break;
-          pending = pending && !ready;
-          done |= m;
-          if (ready) {                         // the pass's list, fields included
-            const uint32_t pos = mbcnt(m);
-            S.plist[pos] = (uint8_t)lane;
-            S.ppk[pos] = mpk;
-            S.pdl[pos] = mdl;
-          }
-          __builtin_amdgcn_wave_barrier();
-          const uint32_t nr = (uint32_t)__popcll(m);
-          for (uint32_t g0 = 0; g0 < nr; g0 += 8) {
-            const uint32_t u = g0 + slot;
-            const bool sv = u < nr;
-            const uint32_t uu = sv ? u : 0u;
-            const uint32_t j = c0 + (uint32_t)S.plist[uu];
-            const uint32_t pkj = S.ppk[uu], dl = S.pdl[uu];
-            const uint32_t dst = dl & 0xFFFFu, len = dl >> 16;
-            const int32_t sj = (int32_t)(pkj & 0xFFFFu) - 16384;
-            const uint32_t dj = (pkj >> 16) & 0x7FFFu;
-            const bool simple = sv && dj >= len && len <= 64;
-            uint32_t v[8];
-            bool below = false;
+    uint8_t* dummy = reinterpret_cast<uint8_t*>(&S.dummy[lane]);
+    const uint32_t* tw = reinterpret_cast<const uint32_t*>(S.tile);
+    for (uint32_t c0 = 0; c0 < cnt; c0 += 64) {
+      const uint32_t a = c0 + lane;
+      const bool have = a < cnt;
+      const uint32_t aa = have ? a : c0;
+      const uint32_t rng = S.lst[aa];
+      const uint32_t plo = rng & 63u, phi = (rng >> 8) & 63u;
+      const uint64_t needm = have && phi > plo ? (1ull << phi) - (1ull << plo) : 0ull;
+      const uint32_t pk = S.oflo[aa];
+      const uint32_t dst = S.lit[aa], len = S.out[aa];
+      const int32_t s = (int32_t)(pk & 0xFFFFu) - 16384;
+      const uint32_t d = (pk >> 16) & 0x7FFFu;
+      const bool fast = d >= len && len <= kFastLen && s >= 0;
+      bool pending = have;
+      uint64_t done = ~__ballot(pending);
+      for (uint32_t pass = 0; pass <= 64; pass++) {
+        const bool ready = pending && (needm & ~done) == 0;
+        const uint64_t m = __ballot(ready);
+        if (!m) break;
+        CLK_ADD(S, 10, 1);
+        const bool rf = ready && fast;
+        if (__ballot(rf)) {
+          // source words covering [s, s + len), realigned to the source start
+          const uint32_t w0 = (uint32_t)max(s, 0) >> 2, o = (uint32_t)max(s, 0) & 3u;
+          uint32_t Wd[kFastLen / 4 + 1];
 #pragma unroll
-            for (uint32_t q = 0; q < 8; q++) {
-              const int32_t src = sj + (int32_t)(sub + 8 * q);
-              v[q] = S.tile[(uint32_t)max(src, 0) & (kB - 1)];
-              below |= simple && sub + 8 * q < len && src < 0;
-            }
-            if (__ballot(below)) {
+          for (uint32_t i = 0; i < kFastLen / 4 + 1; i++) Wd[i] = tw[min(w0 + i, kB / 4 - 1)];
+          uint32_t Al[kFastLen / 4];
 #pragma unroll
-              for (uint32_t q = 0; q < 8; q++) {
-                const int32_t src = sj + (int32_t)(sub + 8 * q);
-                if (simple && sub + 8 * q < len && src < 0) v[q] = src_byte(A, sb + (int64_t)src, bad);
-              }
-            }
+          for (uint32_t i = 0; i < kFastLen / 4; i++) Al[i] = __builtin_amdgcn_alignbyte(Wd[i + 1], Wd[i], o);
+          const uint32_t lim = rf ? len : 0u;
 #pragma unroll
-            for (uint32_t q = 0; q < 8; q++) {
-              const uint32_t k = sub + 8 * q;
-              if (simple && k < len && dst + k < blen) S.tile[dst + k] = (uint8_t)v[q];
-            }
-            uint64_t slow = __ballot(sv && !simple && sub == 0);
-            while (slow) {                     // wave-uniform
-              const uint32_t l = (uint32_t)__builtin_ctzll(slow);
-              slow &= slow - 1;
-              copy_match((uint32_t)__builtin_amdgcn_readlane((int)j, (int)l));
+          for (uint32_t g = 0; g < kFastLen / 4; g++) {
+            if (!__ballot(4 * g < lim)) break;
+#pragma unroll
+            for (uint32_t u = 0; u < 4; u++) {
+              const uint32_t k = 4 * g + u;
+              uint8_t* p = k < lim ? S.tile + dst + k : dummy + u;
+              *p = (uint8_t)(Al[g] >> (8 * u));
             }
           }
-          __builtin_amdgcn_wave_barrier();
         }
-        if (__ballot(pending)) bad = true;      // unreachable for a valid block
+        uint64_t slow = __ballot(ready && !fast);
+        const uint64_t c1_ = CLK_NOW();
+        CLK_ADD(S, 11, __popcll(slow));
+        while (slow) {                        // wave-uniform
+          const uint32_t l = (uint32_t)__builtin_ctzll(slow);
+          slow &= slow - 1;
+          copy_match(c0 + l);
+        }
+        CLK_ADD(S, 12, CLK_NOW() - c1_);
+        pending = pending && !ready;
+        done |= m;
+        // the next pass reads what this one wrote (LDS operations of a wave
+        // are performed in order; the fence keeps the compiler from moving
+        // the reads above the stores)
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       }
+      if (__ballot(pending)) bad = true;      // unreachable for a valid block
     }
     if (bad) S.err = 1;
   }
@@ -777,6 +916,7 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
     if (t == 0) latch(A.ctl, kStCorrupt);
     return;
   }
+  CLK_MARK(S, 7);
 
   // ---- stage 5: tile -> HBM with 16-byte stores
   uint8_t* dst = A.addr ? reinterpret_cast<uint8_t*>(A.addr[b]) : A.out + sb;
@@ -787,6 +927,10 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
     for (uint32_t c = t; c < full; c += kWG) d4[c] = s4[c];
     for (uint32_t c = (full << 4) + t; c < blen; c += kWG) dst[c] = S.tile[c];
   }
+  CLK_MARK(S, 8);
+#ifdef LZ_STAGE_CLOCKS
+  if (t == 0) S.clk[9] += 1;
+#endif
 }
 
 // Once per workgroup: literal LUT image into LDS, small-stream cumulative tables.
@@ -828,6 +972,9 @@ __global__ void __launch_bounds__(kWG, 3) k_decode(DevArgs A) {   // 3 waves per
   __shared__ Smem S;
   const uint32_t t = threadIdx.x;
   load_tables(S, A);
+#ifdef LZ_STAGE_CLOCKS
+  if (t < kClkSlots) S.clk[t] = 0;
+#endif
   __syncthreads();
   const uint32_t epoch = __hip_atomic_load(A.ctl + kCtlEpoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   uint32_t qb = A.q_begin, qe = A.q_end;
@@ -835,39 +982,52 @@ __global__ void __launch_bounds__(kWG, 3) k_decode(DevArgs A) {   // 3 waves per
     qb = A.qptr[A.q_begin];
     qe = A.qptr[A.q_end];
   }
-  if (!A.persistent) {
-    for (uint32_t it = qb + blockIdx.x; it < qe; it += gridDim.x) {
-      decode_block(S, A, A.queue[it]);
+  // blocks of this workgroup: a grid-stride slice of the queue (per-level
+  // launches) or tickets in queue order (persistent launch)
+  uint32_t it = qb + blockIdx.x;
+  for (;;) {
+    if (A.persistent) {
+      if (t == 0) S.item = qb + atomicAdd(A.ctl + kCtlTicket, 1u);
+      __syncthreads();
+      it = S.item;
       __syncthreads();
     }
-    return;
-  }
-  for (;;) {
-    if (t == 0) S.item = qb + atomicAdd(A.ctl + kCtlTicket, 1u);
-    __syncthreads();
-    const uint32_t it = S.item;
-    __syncthreads();
     if (it >= qe) break;
     const uint32_t b = A.queue[it];
-    // wait for every dependency's completion flag, then acquire
-    const uint64_t d0 = ld64(A.arc + A.off_dep_ptr + 8ull * b);
-    const uint64_t d1 = ld64(A.arc + A.off_dep_ptr + 8ull * (b + 1));
-    for (uint64_t k = d0 + t; k < d1; k += kWG) {
-      const uint32_t d = ld32(A.arc + A.off_dep_idx + 4 * k);
-      uint32_t f;
-      for (uint32_t spins = 0;
-           (f = __hip_atomic_load(A.flags + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != epoch; spins++) {
-        if (spins >= A.spin_limit) { watchdog(A.ctl, 1, b, d, f, epoch); break; }
-        __builtin_amdgcn_s_sleep(1);
+    if (A.persistent) {
+      // wait for every dependency's completion flag, then acquire
+      const uint64_t d0 = ld64(A.arc + A.off_dep_ptr + 8ull * b);
+      const uint64_t d1 = ld64(A.arc + A.off_dep_ptr + 8ull * (b + 1));
+      for (uint64_t k = d0 + t; k < d1; k += kWG) {
+        const uint32_t d = ld32(A.arc + A.off_dep_idx + 4 * k);
+        uint32_t f;
+        for (uint32_t spins = 0;
+             (f = __hip_atomic_load(A.flags + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != epoch; spins++) {
+          if (spins >= A.spin_limit || ((spins & 255u) == 255u && watchdog_fired(A.ctl))) {
+            watchdog(A.ctl, 1, b, d, f, epoch);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
       }
+      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     decode_block(S, A, b);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (t == 0) __hip_atomic_store(A.flags + b, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (A.persistent) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __syncthreads();
+      if (t == 0) __hip_atomic_store(A.flags + b, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      __syncthreads();
+      it += gridDim.x;
+    }
   }
+#ifdef LZ_STAGE_CLOCKS
+  __syncthreads();
+  if (t < kClkSlots) atomicAdd(reinterpret_cast<unsigned long long*>(A.ctl + kCtlClock) + t,
+                               (unsigned long long)S.clk[t]);
+#endif
 }
 
 // ---- setup kernels ---------------------------------------------------------

@@ -73,7 +73,8 @@ enum : uint32_t {
   kCtlPairs = 12,     // u64: (request, covering block) pairs of the batch
   kCtlLevelCnt = 16,  // 64 level counters of the closure queue
   kCtlDiag = 80,      // first watchdog: site, block, dependency, seen, expected
-  kCtlWords = 96,
+  kCtlClock = 96,     // u64[16]: stage clocks of an instrumented build (LZ_STAGE_CLOCKS)
+  kCtlWords = 128,
 };
 
 struct lz_handle {
