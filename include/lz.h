@@ -66,6 +66,10 @@ typedef struct lz_params {
   uint32_t kind;          /* 0 raw, 1 FASTQ (writes the read index), 2 FASTA */
   uint32_t level_penalty; /* beta: match score = length - beta * level       */
   uint32_t threads;       /* encoder host threads (0 = all); no effect on bytes */
+  uint32_t segment_log2;  /* 0: the global parse defined above (bytes equal to
+                             the reference policy, memory ~20 B per input byte);
+                             block_log2..24: segmented parse with bounded
+                             memory (see lz_encode), for inputs of many GB    */
 } lz_params;
 
 typedef struct lz_info {
@@ -108,7 +112,14 @@ int lz_params_default(lz_params* p);
 
 /* Compress src[0..n) (host memory).  On success *archive (host memory owned by
  * the library, free with lz_free) holds *archive_len bytes.  Errors: EINVAL
- * (bad parameters, or kind FASTQ and the input is not whole 4-line records). */
+ * (bad parameters, or kind FASTQ and the input is not whole 4-line records).
+ * With segment_log2 > 0 the input is parsed in segments of 2^segment_log2
+ * bytes on host threads: a match source is an earlier position of the same
+ * segment (hash chain, most recent first) or the first position ever seen with
+ * the same hash, if that lies 32 or more segments back; the scoring and level
+ * rules are those of the global parse.  The output does not depend on the
+ * thread count; working memory is bounded by the segment size, the hash table
+ * (8 B x 2^hash_bits) and the archive itself. */
 int lz_encode(const uint8_t* src, uint64_t n, const lz_params* p,
               uint8_t** archive, uint64_t* archive_len);
 void lz_free(void* p);
@@ -188,6 +199,24 @@ int lz_decode_batch(lz_handle* h, const lz_request* d_reqs, const uint32_t* d_n,
  * tree hash.  d_scratch needs 8 * n_blocks bytes. */
 int lz_verify(lz_handle* h, const uint8_t* d_out, uint64_t* d_tree,
               void* d_scratch, uint64_t scratch_len, hipStream_t s);
+
+/* The same check for a decoded part of the file: d_out holds x[offset,
+ * offset+len), offset a multiple of the block size and len one too unless the
+ * range ends at N (EINVAL otherwise); every block of the range is hashed and
+ * compared with its source hash (mismatch latched as ECORRUPT).  d_scratch
+ * needs 8 bytes per block of the range. */
+int lz_verify_range(lz_handle* h, const uint8_t* d_out, uint64_t offset, uint64_t len,
+                    void* d_scratch, uint64_t scratch_len, hipStream_t s);
+
+/* Work of the last request call on h (lz_decode_range, lz_read_lookup,
+ * lz_read_lookup_noalloc, lz_decode_batch): closure_blocks = blocks decoded
+ * (the covering blocks plus their dependency closure, Position-Invariant
+ * Random Access section), scratch_slots = those decoded into scratch, covering
+ * = (request, covering block) pairs.  Synchronises s. */
+typedef struct lz_stats {
+  uint64_t closure_blocks, scratch_slots, covering;
+} lz_stats;
+int lz_last_stats(lz_handle* h, lz_stats* out, hipStream_t s);
 
 /* Synchronise s, return and clear the latched device status (LZ_OK if none). */
 int lz_sync_status(lz_handle* h, hipStream_t s);

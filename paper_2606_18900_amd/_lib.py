@@ -20,7 +20,7 @@ NAMES = {0: "LZ_OK", -1: "LZ_EINVAL", -2: "LZ_EFORMAT", -3: "LZ_ECAPACITY", -4: 
 # every symbol include/lz.h declares
 EXPORTS = ["lz_params_default", "lz_encode", "lz_free", "lz_info_get", "lz_open", "lz_close",
            "lz_get_info", "lz_set_tuning", "lz_get_tuning", "lz_decode_all", "lz_decode_range",
-           "lz_read_lookup", "lz_read_lookup_noalloc", "lz_decode_batch", "lz_verify", "lz_sync_status", "lz_last_error"]
+           "lz_read_lookup", "lz_read_lookup_noalloc", "lz_decode_batch", "lz_verify", "lz_verify_range", "lz_last_stats", "lz_sync_status", "lz_last_error"]
 
 
 class LzError(RuntimeError):
@@ -36,7 +36,7 @@ class Params(C.Structure):
                 ("window_log2", C.c_uint32), ("lit_lanes", C.c_uint32),
                 ("seq_lanes", C.c_uint32), ("prob_bits", C.c_uint32 * 4),
                 ("kind", C.c_uint32), ("level_penalty", C.c_uint32),
-                ("threads", C.c_uint32)]
+                ("threads", C.c_uint32), ("segment_log2", C.c_uint32)]
 
 
 class Info(C.Structure):
@@ -51,6 +51,10 @@ class Info(C.Structure):
 
 class Request(C.Structure):
     _fields_ = [("kind", C.c_int64), ("a", C.c_int64), ("b", C.c_int64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("closure_blocks", C.c_uint64), ("scratch_slots", C.c_uint64), ("covering", C.c_uint64)]
 
 
 class Tuning(C.Structure):
@@ -82,6 +86,8 @@ def lib():
         L.lz_read_lookup_noalloc.argtypes = [vp, vp, u64, vp, u64, vp, vp]
         L.lz_decode_batch.argtypes = [vp, vp, vp, u64, vp, u64, vp, vp, u64, vp]
         L.lz_verify.argtypes = [vp, vp, vp, vp, u64, vp]
+        L.lz_verify_range.argtypes = [vp, vp, u64, u64, vp, u64, vp]
+        L.lz_last_stats.argtypes = [vp, vp, vp]
         L.lz_sync_status.argtypes = [vp, vp]
         L.lz_free.argtypes = [vp]
         L.lz_params_default.argtypes = [vp]

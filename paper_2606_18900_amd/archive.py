@@ -25,7 +25,9 @@ def encode(data, **params) -> bytes:
     check(lib().lz_encode(C.c_void_p(a.ctypes.data if a.size else 0), a.size, C.byref(p),
                           C.byref(out), C.byref(n)))
     try:
-        return C.string_at(out.value, n.value)
+        if not n.value:
+            return b""
+        return bytes(memoryview((C.c_char * n.value).from_address(out.value)))   # any size
     finally:
         lib().lz_free(out)
 
@@ -56,7 +58,10 @@ class Archive:
             self.d_archive = archive
             head = archive[:128].cpu().numpy().tobytes()
         else:
-            host = torch.frombuffer(bytearray(archive), dtype=torch.uint8)
+            import warnings
+            with warnings.catch_warnings():   # read-only host bytes: copied, never written
+                warnings.simplefilter("ignore")
+                host = torch.from_numpy(np.frombuffer(archive, dtype=np.uint8))
             self.d_archive = torch.empty(host.numel(), dtype=torch.uint8, device=self.device)
             self.d_archive.copy_(host)
             head = bytes(archive[:128])
@@ -205,6 +210,24 @@ class Archive:
         check(lib().lz_verify(self.h, _ptr(out), _ptr(tree), _ptr(scratch), scratch.numel(),
                               _stream(stream)))
         return tree
+
+    def verify_range(self, out: torch.Tensor, offset: int, length: int,
+                     scratch: torch.Tensor | None = None, stream=None) -> None:
+        """lz_verify_range: every block of x[offset, offset+length), decoded at
+        out, against its source hash (a mismatch surfaces in sync_status)."""
+        B = 1 << int(self.info.block_log2)
+        need = max(8, 8 * (-(-length // B)))
+        if scratch is None or scratch.numel() < need:
+            scratch = torch.empty(need, dtype=torch.uint8, device=self.device)
+        check(lib().lz_verify_range(self.h, _ptr(out), offset, length, _ptr(scratch), scratch.numel(),
+                                    _stream(stream)))
+
+    def last_stats(self, stream=None) -> _lib.Stats:
+        """lz_last_stats: blocks decoded by the last request call (covering
+        blocks plus dependency closure), scratch slots, covering pairs."""
+        st = _lib.Stats()
+        check(lib().lz_last_stats(self.h, C.byref(st), _stream(stream)))
+        return st
 
     def sync_status(self, stream=None) -> None:
         check(lib().lz_sync_status(self.h, _stream(stream)))

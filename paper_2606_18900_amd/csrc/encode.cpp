@@ -21,6 +21,9 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
+#include <mutex>
+#include <new>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
@@ -50,7 +53,9 @@ struct Hasher {
     mask1 = n1 == 8 ? ~0ull : ((1ull << (8 * n1)) - 1);
   }
   // requires p + h <= n; reads exactly h bytes unless 16 are available
-  inline uint64_t operator()(const uint8_t* x, uint64_t p, uint64_t n) const {
+  inline uint64_t operator()(const uint8_t* x, uint64_t p, uint64_t n) const { return mix(x, p, n) >> (64 - H); }
+  // the 64-bit value whose top H bits are the hash
+  inline uint64_t mix(const uint8_t* x, uint64_t p, uint64_t n) const {
     uint64_t v0, v1;
     if (p + 16 <= n) {
       std::memcpy(&v0, x + p, 8);
@@ -63,7 +68,7 @@ struct Hasher {
     }
     uint64_t t = v0 * kGolden;
     t = (t << 29) | (t >> 35);
-    return ((t ^ v1) * kGolden) >> (64 - H);
+    return (t ^ v1) * kGolden;
   }
 };
 
@@ -272,6 +277,210 @@ int parse_impl(const uint8_t* x, uint64_t n, const lz_params& pr, unsigned threa
   return LZ_OK;
 }
 
+// Segmented parse (segment_log2 > 0), for inputs too large for the global
+// parse's per-position tables.  Segments of S = 2^segment_log2 bytes (whole
+// blocks) are taken in order by host threads.  Segment s looks for sources in
+//   (a) its own earlier positions whose hash has the same low 18 bits and
+//       the same 8 bits above them: the min(C, 4) most recent ones (a 4-way
+//       bucket of 24-bit segment positions with the 8 bits beside them, most
+//       recent first), none older than 2^window_log2 when set;
+//   (b) per hash, the first position ever seen, when it lies in a segment
+//       s - kSegLag or earlier.  The table entry also keeps 24 further bits of
+//       that position's hash, so a position whose hash only shares the top
+//       bits is not read.
+// Before segment s starts, every segment up to s - kSegLag is complete, so
+// (b) finds the same position whatever the threads' timing, and every level
+// the scoring needs is final: the archive depends only on the input and the
+// parameters.  Scoring, tie-breaking and the level cap are those of the
+// global parse.  Hashes are computed a block ahead and the table lines of
+// position p + kAhead are prefetched while p is parsed.
+constexpr uint64_t kSegLag = 32;
+constexpr uint32_t kWays = 4;
+constexpr uint64_t kAhead = 32;
+
+int parse_segmented(const uint8_t* x, uint64_t n, const lz_params& pr, unsigned threads, Parse& out) {
+  const uint32_t bl = pr.block_log2;
+  const uint64_t B = 1ull << bl, nb = (n + B - 1) >> bl;
+  const uint32_t h = pr.hash_len, m = pr.min_match, D = pr.max_level;
+  const uint32_t H = std::min<uint32_t>(pr.hash_bits, 28);
+  const uint32_t HL = 18;                                   // per-segment buckets
+  const uint64_t C = std::min<uint64_t>(pr.chain_depth ? pr.chain_depth : kWays, kWays);
+  const uint64_t win = pr.window_log2 ? (1ull << pr.window_log2) : ~0ull;
+  const int64_t beta = pr.level_penalty;
+  const uint32_t sl = pr.segment_log2;
+  const uint64_t S = 1ull << sl, nseg = (n + S - 1) >> sl;
+  const Hasher hash(h, H);
+  // first-seen entries: 24 tag bits << 40 | position (positions below 2^40)
+  constexpr uint64_t kNone = ~0ull, kPosMask = (1ull << 40) - 1;
+  if (n >= kPosMask) return LZ_EINVAL;
+  std::unique_ptr<std::atomic<uint64_t>[]> first(new (std::nothrow) std::atomic<uint64_t>[1ull << H]);
+  if (!first) return LZ_EINVAL;
+  parallel_for(1ull << (H > 20 ? H - 20 : 0), threads, [&](uint64_t c, unsigned) {
+    const uint64_t lo = c << 20, hi = std::min<uint64_t>(1ull << H, lo + (1ull << 20));
+    for (uint64_t i = lo; i < hi; i++) first[i].store(kNone, std::memory_order_relaxed);
+  });
+  auto tag_of = [&](uint64_t mx) -> uint64_t { return ((mx >> (40 - H)) & 0xFFFFFFull) << 40; };
+  struct BlockOut {
+    std::vector<uint32_t> ll, ml, deps;
+    std::vector<uint64_t> of;
+  };
+  std::vector<BlockOut> bo(nb);
+  out.level.assign(nb, 0);
+  std::unique_ptr<std::atomic<uint8_t>[]> seg_done(new std::atomic<uint8_t>[nseg ? nseg : 1]);
+  for (uint64_t i = 0; i < nseg; i++) seg_done[i].store(0, std::memory_order_relaxed);
+  std::atomic<uint64_t> next{0}, low{0};     // low: every segment below it is complete
+  std::mutex mu;
+  auto finish = [&](uint64_t sg) {
+    seg_done[sg].store(1, std::memory_order_release);
+    std::lock_guard<std::mutex> g(mu);
+    uint64_t w = low.load(std::memory_order_relaxed);
+    while (w < nseg && seg_done[w].load(std::memory_order_acquire)) w++;
+    low.store(w, std::memory_order_release);
+  };
+  auto work = [&]() {
+    // bucket k: entries [kWays k, kWays k + kWays): 8 tag bits << 24 |
+    // (position - s0 + 1); 0 = empty
+    std::vector<uint32_t> bkt((size_t)kWays << HL);
+    std::vector<uint64_t> hv(B + kAhead);
+    const uint64_t lmask = (1ull << HL) - 1;
+    for (;;) {
+      const uint64_t sg = next.fetch_add(1);
+      if (sg >= nseg) break;
+      const uint64_t need = sg >= kSegLag ? sg - kSegLag + 1 : 0;
+      while (low.load(std::memory_order_acquire) < need) std::this_thread::sleep_for(std::chrono::microseconds(50));
+      const uint64_t s0 = sg << sl, s1 = std::min(n, s0 + S);
+      const uint64_t far = need << sl;           // first-seen sources must lie below this
+      std::fill(bkt.begin(), bkt.end(), 0u);
+      const uint64_t nh = n >= h ? n - h + 1 : 0;   // positions with a hash
+      uint64_t ins = s0;                             // next position to insert
+      for (uint64_t b = s0 >> bl; b << bl < s1; b++) {
+        BlockOut& o = bo[b];
+        const uint64_t sb = b << bl, eb = std::min(sb + B, n);
+        // hashes of [sb, eb + kAhead) within the segment
+        const uint64_t he = std::min({eb + kAhead, s1, nh});
+        for (uint64_t q = sb; q < he; q++) hv[q - sb] = hash.mix(x, q, n);
+        auto hash_at = [&](uint64_t q) -> uint64_t { return hv[q - sb] >> (64 - H); };
+        // bucket of the low 18 bits of the 64-bit mix, tag of the 8 above
+        auto bucket_at = [&](uint64_t q) -> uint64_t { return hv[q - sb] & lmask; };
+        auto btag_at = [&](uint64_t q) -> uint32_t { return (uint32_t)((hv[q - sb] >> HL) & 0xFFu) << 24; };
+        auto prefetch = [&](uint64_t q) {
+          if (q < he) {
+            __builtin_prefetch(&bkt[bucket_at(q) * kWays], 1);
+            __builtin_prefetch(&first[hash_at(q)], 1);
+          }
+        };
+        auto insert_to = [&](uint64_t e) {
+          for (; ins < e && ins < nh; ins++) {
+            prefetch(ins + kAhead);
+            const uint64_t hq = hash_at(ins);
+            uint32_t* bk = &bkt[bucket_at(ins) * kWays];
+            for (uint32_t w = kWays - 1; w; w--) bk[w] = bk[w - 1];
+            bk[0] = btag_at(ins) | (uint32_t)(ins - s0 + 1);
+            std::atomic<uint64_t>& f = first[hq];
+            const uint64_t mine = tag_of(hv[ins - sb]) | ins;
+            uint64_t cur = f.load(std::memory_order_relaxed);
+            while ((cur & kPosMask) > ins && !f.compare_exchange_weak(cur, mine, std::memory_order_relaxed)) {
+            }
+          }
+          if (ins < e) ins = e;
+        };
+        uint64_t p = sb, lit = sb;
+        uint32_t blevel = 0;
+        while (p < eb) {
+          insert_to(p);
+          prefetch(p + kAhead);
+          uint64_t bestL = 0, bestQ = 0;
+          uint32_t bestLv = 0;
+          int64_t bestSc = 0;
+          if (p + m <= eb) {
+            const uint64_t hp = hash_at(p);
+            auto consider = [&](uint64_t q) {
+              const uint64_t L = lcp(x, q, p, eb - p);
+              if (L < m) return;
+              uint32_t lv = 0;
+              if (q < sb) {
+                const uint64_t hi = std::min(q + L, sb);
+                uint32_t mx = 0;
+                for (uint64_t k = q >> bl; k <= (hi - 1) >> bl; k++) mx = std::max<uint32_t>(mx, out.level[k]);
+                lv = mx + 1;
+              }
+              if (lv > D - 1) return;
+              const int64_t sc = (int64_t)L - beta * (int64_t)lv;
+              if (sc < (int64_t)m) return;
+              if (bestL == 0 || sc > bestSc || (sc == bestSc && lv < bestLv)) {
+                bestSc = sc;
+                bestL = L;
+                bestQ = q;
+                bestLv = lv;
+              }
+            };
+            // (a) own segment, most recent first
+            const uint32_t* bk = &bkt[bucket_at(p) * kWays];
+            const uint32_t tg = btag_at(p);
+            for (uint64_t c = 0; c < C && bk[c]; c++) {
+              const uint64_t q = s0 + (bk[c] & 0xFFFFFFu) - 1;
+              if (p - q > win) break;
+              if ((bk[c] & 0xFF000000u) == tg) consider(q);
+            }
+            // (b) first position seen with this hash, kSegLag or more segments back
+            const uint64_t fa = first[hp].load(std::memory_order_relaxed);
+            const uint64_t a = fa & kPosMask;
+            if (fa != kNone && (fa & ~kPosMask) == tag_of(hv[p - sb]) && a < far) consider(a);
+          }
+          if (bestL) {
+            o.ll.push_back((uint32_t)(p - lit));
+            o.ml.push_back((uint32_t)bestL);
+            o.of.push_back(bestQ);
+            if (bestQ < sb) {
+              const uint64_t hi = std::min(bestQ + bestL, sb);
+              for (uint64_t k = bestQ >> bl; k <= (hi - 1) >> bl; k++) o.deps.push_back((uint32_t)k);
+            }
+            blevel = std::max(blevel, bestLv);
+            p += bestL;
+            lit = p;
+          } else {
+            p++;
+          }
+        }
+        insert_to(eb);
+        if (lit < eb) {
+          o.ll.push_back((uint32_t)(eb - lit));
+          o.ml.push_back(0);
+          o.of.push_back(0);
+        }
+        std::sort(o.deps.begin(), o.deps.end());
+        o.deps.erase(std::unique(o.deps.begin(), o.deps.end()), o.deps.end());
+        out.level[b] = (uint16_t)blevel;
+      }
+      finish(sg);
+    }
+  };
+  {
+    std::vector<std::thread> ts;
+    for (unsigned t = 1; t < threads; t++) ts.emplace_back(work);
+    work();
+    for (auto& t : ts) t.join();
+  }
+  out.seq_ptr.assign(nb + 1, 0);
+  out.dep_ptr.assign(nb + 1, 0);
+  for (uint64_t b = 0; b < nb; b++) {
+    out.seq_ptr[b + 1] = out.seq_ptr[b] + bo[b].ll.size();
+    out.dep_ptr[b + 1] = out.dep_ptr[b] + bo[b].deps.size();
+  }
+  out.ll.resize(out.seq_ptr[nb]);
+  out.ml.resize(out.seq_ptr[nb]);
+  out.of.resize(out.seq_ptr[nb]);
+  out.dep_idx.resize(out.dep_ptr[nb]);
+  parallel_for(nb, threads, [&](uint64_t b, unsigned) {
+    std::copy(bo[b].ll.begin(), bo[b].ll.end(), out.ll.begin() + out.seq_ptr[b]);
+    std::copy(bo[b].ml.begin(), bo[b].ml.end(), out.ml.begin() + out.seq_ptr[b]);
+    std::copy(bo[b].of.begin(), bo[b].of.end(), out.of.begin() + out.seq_ptr[b]);
+    std::copy(bo[b].deps.begin(), bo[b].deps.end(), out.dep_idx.begin() + out.dep_ptr[b]);
+    bo[b] = BlockOut();
+  });
+  return LZ_OK;
+}
+
 // ---------------------------------------------------------------- rANS
 // Normalise counts to sum 2^P (floor(c*M/T), at least 1 per seen symbol;
 // remainder to the most frequent symbol, lowest value on ties; an excess is
@@ -441,6 +650,7 @@ int check(const lz_params& p) {
   for (int k = 0; k < 4; k++)
     if (p.prob_bits[k] < 8 || p.prob_bits[k] > 12) return LZ_EINVAL;
   if (p.kind > 2 || p.level_penalty > 255) return LZ_EINVAL;
+  if (p.segment_log2 && (p.segment_log2 < p.block_log2 || p.segment_log2 > 24)) return LZ_EINVAL;
   return LZ_OK;
 }
 
@@ -462,6 +672,7 @@ extern "C" int lz_params_default(lz_params* p) {
   p->kind = 0;
   p->level_penalty = 32;
   p->threads = 0;
+  p->segment_log2 = 0;
   return LZ_OK;
 }
 
@@ -502,7 +713,9 @@ extern "C" int lz_encode(const uint8_t* x, uint64_t n, const lz_params* pp, uint
     }
   }
   Parse ps;
-  int rc = n < (1ull << 32) - 1 ? parse_impl<uint32_t>(x, n, pr, threads, ps) : parse_impl<uint64_t>(x, n, pr, threads, ps);
+  int rc = pr.segment_log2 ? parse_segmented(x, n, pr, threads, ps)
+           : n < (1ull << 32) - 1 ? parse_impl<uint32_t>(x, n, pr, threads, ps)
+                                  : parse_impl<uint64_t>(x, n, pr, threads, ps);
   if (rc) return lz_fail(rc, "lz_encode: parse failed");
 
   // per-block stream bytes, built on demand
@@ -526,11 +739,21 @@ extern "C" int lz_encode(const uint8_t* x, uint64_t n, const lz_params* pp, uint
     }
   };
   std::vector<std::vector<uint64_t>> cnt(threads, std::vector<uint64_t>(4 * 256, 0));
-  parallel_for(nb, threads, [&](uint64_t b, unsigned t) {
-    std::vector<uint8_t> s[4];
-    build(b, s);
-    for (int k = 0; k < 4; k++)
-      for (uint8_t v : s[k]) cnt[t][k * 256 + v]++;
+  parallel_for(nb, threads, [&](uint64_t b, unsigned t) {   // symbol counts of the four streams
+    uint64_t* c = cnt[t].data();
+    const uint64_t s0 = ps.seq_ptr[b], ns = ps.seq_ptr[b + 1] - s0;
+    uint64_t pos = b << bl;
+    for (uint64_t j = 0; j < ns; j++) {
+      const uint32_t L = ps.ll[s0 + j], M = ps.ml[s0 + j];
+      const uint64_t O = ps.of[s0 + j];
+      for (uint64_t i = 0; i < L; i++) c[kLit * 256 + x[pos + i]]++;
+      pos += (uint64_t)L + M;
+      c[kCmd * 256 + (L & 0xFF)]++;
+      c[kCmd * 256 + ((L >> 8) & 0xFF)]++;
+      c[kMlen * 256 + (M & 0xFF)]++;
+      c[kMlen * 256 + ((M >> 8) & 0xFF)]++;
+      for (uint32_t k = 0; k < w; k++) c[kOff * 256 + ((O >> (8 * k)) & 0xFF)]++;
+    }
   });
   Table tab[4];
   for (int k = 0; k < 4; k++) {

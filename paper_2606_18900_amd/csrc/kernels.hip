@@ -1146,25 +1146,30 @@ int lz_launch_decode_all(lz_handle* h, uint8_t* out, hipStream_t s) {
 // ---- verification: per-block FNV-1a-64 against the directory -----------------
 namespace {
 
+// Blocks b0 .. b0 + nb - 1 of the file, decoded at out (block b0 first): one
+// thread per block hashes it with FNV-1a-64 and compares the hash with the
+// directory's source hash.
 __global__ void k_fnv_blocks(const uint8_t* arc, uint64_t off_dir, const uint8_t* out, uint64_t n,
-                             uint32_t bl, uint64_t nb, uint64_t* hashes, uint32_t* ctl) {
-  const uint64_t b = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (b >= nb) return;
+                             uint32_t bl, uint64_t b0, uint64_t nb, uint64_t* hashes, uint32_t* ctl) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const uint64_t b = b0 + i;
   const uint64_t sb = b << bl, B = 1ull << bl;
   const uint64_t len = sb + B <= n ? B : n - sb;
+  const uint8_t* src = out + (i << bl);
   uint64_t h = kFnvBasis;
-  const uint4* p = reinterpret_cast<const uint4*>(out + sb);
-  uint64_t i = 0;
-  for (; i + 16 <= len; i += 16) {
-    const uint4 v = p[i >> 4];
+  const uint4* p = reinterpret_cast<const uint4*>(src);
+  uint64_t k = 0;
+  for (; k + 16 <= len; k += 16) {
+    const uint4 v = p[k >> 4];
     const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int q = 0; q < 4; q++)
 #pragma unroll
-      for (int k = 0; k < 4; k++) h = (h ^ ((w[q] >> (8 * k)) & 0xFFu)) * kFnvPrime;
+      for (int j = 0; j < 4; j++) h = (h ^ ((w[q] >> (8 * j)) & 0xFFu)) * kFnvPrime;
   }
-  for (; i < len; i++) h = (h ^ out[sb + i]) * kFnvPrime;
-  hashes[b] = h;
+  for (; k < len; k++) h = (h ^ src[k]) * kFnvPrime;
+  hashes[i] = h;
   if (h != ld64(arc + off_dir + b * kDirEntry + 24)) latch(ctl, kStHash);
 }
 
@@ -1179,15 +1184,15 @@ __global__ void k_fnv_tree(const uint64_t* hashes, uint64_t nb, uint64_t* tree) 
 
 }  // namespace
 
-int lz_launch_verify(lz_handle* h, const uint8_t* d_out, uint64_t* d_tree, void* scratch, hipStream_t s) {
-  const uint64_t nb = h->av.n_blocks;
+int lz_launch_verify(lz_handle* h, const uint8_t* d_out, uint64_t b0, uint64_t nb, uint64_t* d_tree,
+                     void* scratch, hipStream_t s) {
   uint64_t* hashes = reinterpret_cast<uint64_t*>(scratch);
   if (nb) {
     if ((uintptr_t)d_out & 15) return lz_fail(LZ_EINVAL, "lz_verify: output must be 16-byte aligned");
     hipLaunchKernelGGL(k_fnv_blocks, dim3((uint32_t)((nb + 255) / 256)), dim3(256), 0, s, h->av.base,
-                       h->av.off_dir, d_out, h->av.n, h->av.block_log2, nb, hashes, h->ws.ctl);
+                       h->av.off_dir, d_out, h->av.n, h->av.block_log2, b0, nb, hashes, h->ws.ctl);
   }
-  hipLaunchKernelGGL(k_fnv_tree, dim3(1), dim3(1), 0, s, hashes, nb, d_tree);
+  if (d_tree) hipLaunchKernelGGL(k_fnv_tree, dim3(1), dim3(1), 0, s, hashes, nb, d_tree);
   return launch_ok("lz_verify");
 }
 

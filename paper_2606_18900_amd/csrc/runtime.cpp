@@ -28,7 +28,8 @@ extern "C" const char* lz_last_error(void) { return g_err; }
 size_t lz_decode_smem_bytes();
 int lz_launch_setup(lz_handle* h, hipStream_t s);
 int lz_launch_decode_all(lz_handle* h, uint8_t* out, hipStream_t s);
-int lz_launch_verify(lz_handle* h, const uint8_t* d_out, uint64_t* d_tree, void* scratch, hipStream_t s);
+int lz_launch_verify(lz_handle* h, const uint8_t* d_out, uint64_t b0, uint64_t nb, uint64_t* d_tree,
+                     void* scratch, hipStream_t s);
 int lz_noalloc_setup(int dev, void** ptr);
 int lz_launch_requests(lz_handle* h, const lz_request* d_reqs, const uint32_t* d_n, uint64_t n_max,
                        uint64_t single_off, uint64_t single_len, const int64_t* d_ids,
@@ -358,11 +359,37 @@ extern "C" int lz_sync_status(lz_handle* h, hipStream_t s) {
   return lz_fail(LZ_ECORRUPT, "device: decode check failed (status 0x%x)", st);
 }
 
+extern "C" int lz_last_stats(lz_handle* h, lz_stats* out, hipStream_t s) {
+  if (!h || !out) return lz_fail(LZ_EINVAL, "lz_last_stats: null");
+  uint32_t ctl[kCtlPairs + 2];
+  int rc = hip_check(hipMemcpyAsync(ctl, h->ws.ctl, sizeof(ctl), hipMemcpyDeviceToHost, s), "lz_last_stats: copy");
+  if (!rc) rc = hip_check(hipStreamSynchronize(s), "lz_last_stats: sync");
+  if (rc) return rc;
+  out->closure_blocks = ctl[kCtlListTail];
+  out->scratch_slots = ctl[kCtlSlots];
+  out->covering = (uint64_t)ctl[kCtlPairs] | ((uint64_t)ctl[kCtlPairs + 1] << 32);
+  return LZ_OK;
+}
+
 extern "C" int lz_verify(lz_handle* h, const uint8_t* d_out, uint64_t* d_tree, void* d_scratch,
                          uint64_t scratch_len, hipStream_t s) {
   if (!h || !d_tree || (!d_out && h->av.n)) return lz_fail(LZ_EINVAL, "lz_verify: null argument");
   if (scratch_len < 8 * h->av.n_blocks || (!d_scratch && h->av.n_blocks)) return lz_fail(LZ_ECAPACITY, "lz_verify: scratch needs %llu bytes", (unsigned long long)(8 * h->av.n_blocks));
-  return lz_launch_verify(h, d_out, d_tree, d_scratch, s);
+  return lz_launch_verify(h, d_out, 0, h->av.n_blocks, d_tree, d_scratch, s);
+}
+
+extern "C" int lz_verify_range(lz_handle* h, const uint8_t* d_out, uint64_t offset, uint64_t len,
+                               void* d_scratch, uint64_t scratch_len, hipStream_t s) {
+  if (!h) return lz_fail(LZ_EINVAL, "lz_verify_range: null handle");
+  const uint64_t N = h->av.n, B = 1ull << h->av.block_log2;
+  if (offset > N || len > N - offset) return lz_fail(LZ_ERANGE, "lz_verify_range: range outside the file");
+  if (!len) return LZ_OK;
+  if (!d_out) return lz_fail(LZ_EINVAL, "lz_verify_range: null output");
+  if (offset % B || (offset + len != N && len % B))
+    return lz_fail(LZ_EINVAL, "lz_verify_range: range must cover whole blocks");
+  const uint64_t nb = (len + B - 1) / B;
+  if (scratch_len < 8 * nb || !d_scratch) return lz_fail(LZ_ECAPACITY, "lz_verify_range: scratch needs %llu bytes", (unsigned long long)(8 * nb));
+  return lz_launch_verify(h, d_out, offset / B, nb, nullptr, d_scratch, s);
 }
 
 extern "C" int lz_decode_range(lz_handle* h, uint64_t offset, uint64_t len, uint8_t* d_out,

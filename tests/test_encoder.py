@@ -66,3 +66,38 @@ def test_library_exports_every_declared_symbol(have_lib):
     L = _lib.lib()
     for name in declared:
         assert hasattr(L, name), name
+
+
+def test_segmented_parse_round_trip_and_thread_independence(have_lib):
+    """The segmented parse (bounded memory, for inputs of many GB) writes an
+    archive that the oracle decodes to the input, whose bytes do not depend on
+    the thread count, and whose sources from earlier segments lie at least 32
+    segments back (segments of one block here, so that rule is exercised)."""
+    import oracle
+    import paper_2606_18900_amd as lz
+    from gen.fasta import fasta
+    x = fasta(3_000_000, seed=3)
+    p = dict(kind=2, block_log2=12, segment_log2=12, hash_bits=20, chain_depth=4)
+    a1 = lz.encode(x, threads=1, **p)
+    a8 = lz.encode(x, threads=8, **p)
+    assert a1 == a8
+    rc, y = oracle.decode(a1)
+    assert rc == 0 and y == x
+    assert len(a1) < len(x) / 2           # repeats are still found
+    # segments are one block here: every dependency of block b lies 32 or
+    # more blocks back (read from the archive's dependency lists)
+    import numpy as np
+    u64 = lambda o: int.from_bytes(a1[o:o + 8], "little")
+    nb, off_ptr, off_idx = u64(32), u64(72), u64(80)
+    ptr = np.frombuffer(a1, dtype=np.uint64, count=nb + 1, offset=off_ptr).astype(np.int64)
+    idx = np.frombuffer(a1, dtype=np.uint32, count=int(ptr[-1]), offset=off_idx).astype(np.int64)
+    owner = np.repeat(np.arange(nb), np.diff(ptr))
+    assert idx.size > 0 and np.all(owner - idx >= 32)
+
+
+def test_segmented_parse_rejects_bad_segment_size(have_lib):
+    import paper_2606_18900_amd as lz
+    with pytest.raises(Exception):
+        lz.encode(b"x" * 1000, block_log2=14, segment_log2=13)   # smaller than a block
+    with pytest.raises(Exception):
+        lz.encode(b"x" * 1000, segment_log2=25)

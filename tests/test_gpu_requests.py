@@ -48,7 +48,7 @@ def _ws_view(arc):
     nb = arc.n_blocks
     sizes = [("lut", 4096 * 4), ("queue", 4 * nb), ("level_ptr", 4 * 65), ("flags", 4 * nb),
              ("mark", 4 * nb), ("addr", 8 * nb), ("rqueue", 4 * nb), ("rlevel_ptr", 4 * 130),
-             ("list", 8 * nb), ("ctl", 4 * 96)]
+             ("list", 8 * nb), ("ctl", 4 * 128)]
     ws = arc.ws.cpu().numpy()
     out, o = {}, 0
     for name, sz in sizes:
@@ -281,3 +281,33 @@ def test_range_with_swapped_dependency_is_corrupt(orc, lz):
             _sync(arc)
         assert e.value.code == lz._lib.LZ_ECORRUPT
         assert _range(arc, 0, 1000, mode) == x[:1000]
+
+
+def test_verify_range_and_last_stats(fq, lz):
+    """lz_verify_range accepts a correctly decoded block-aligned window and
+    latches ECORRUPT for one altered byte; lz_last_stats counts the window's
+    covering blocks plus their dependency closure."""
+    from paper_2606_18900_amd import _lib
+    x, starts, arc = fq
+    B = 1 << int(arc.info.block_log2)
+    o, L = 37 * B, 40 * B
+    out = arc.decode_range(o, L)
+    st = arc.last_stats()
+    _sync(arc)
+    assert out.cpu().numpy().tobytes() == x[o:o + L]
+    assert st.closure_blocks >= 40 and st.covering == 40
+    arc.verify_range(out, o, L)
+    _sync(arc)
+    # the tail window ends at N and need not be whole blocks
+    t0 = (arc.n // B - 2) * B
+    tail = arc.decode_range(t0, arc.n - t0)
+    arc.verify_range(tail, t0, arc.n - t0)
+    _sync(arc)
+    out[12345] ^= 1
+    arc.verify_range(out, o, L)
+    torch.cuda.synchronize()
+    with pytest.raises(_lib.LzError) as e:
+        arc.sync_status()
+    assert e.value.code == _lib.LZ_ECORRUPT
+    with pytest.raises(_lib.LzError):
+        arc.verify_range(out, o + 1, L - B)           # not block-aligned
