@@ -217,6 +217,41 @@ def genome_leg(args) -> int:
 BIG_GENOME_PARAMS = dict(GENOME_PARAMS, hash_bits=26, chain_depth=4, segment_log2=24)
 
 
+def end_to_end(arc, a: bytes, N: int, dev, steps: int = 5):
+    """Honest end-to-end figure beside the device-resident one (paper: Honest
+    End-to-End with PCIe): pinned host archive -> device (H2D), whole-file
+    decode, device output -> pinned host buffer (D2H), all on one stream and
+    timed with HIP events; median of `steps` passes."""
+    import numpy as np
+    import torch
+    h_arc = torch.empty(len(a), dtype=torch.uint8, pin_memory=True)
+    h_arc.numpy()[:] = np.frombuffer(a, dtype=np.uint8)
+    h_out = torch.empty(N, dtype=torch.uint8, pin_memory=True)
+    d_out = torch.empty(N + 256, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    res = []
+    for _ in range(steps + 1):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record(stream)
+        arc.d_archive.copy_(h_arc, non_blocking=True)          # H2D
+        ev[1].record(stream)
+        arc.decode_all(d_out)
+        ev[2].record(stream)
+        h_out.copy_(d_out[:N], non_blocking=True)               # D2H
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        res.append([ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])])
+    arc.sync_status()
+    h2d, dec, d2h = (float(np.median([r[k] for r in res[1:]])) for k in range(3))
+    tot = h2d + dec + d2h
+    return {"GB_per_s": round(N / (tot / 1e3) / 1e9, 2), "total_ms": round(tot, 3),
+            "h2d_ms": round(h2d, 3), "h2d_GB_per_s": round(len(a) / (h2d / 1e3) / 1e9, 2),
+            "decode_ms": round(dec, 3), "d2h_ms": round(d2h, 3),
+            "d2h_GB_per_s": round(N / (d2h / 1e3) / 1e9, 2),
+            "what": "pinned H2D of the archive + whole-file decode + pinned D2H of the output, "
+                    "one stream, median of %d" % steps}
+
+
 def big_genome_leg(args, dev):
     """Range decode of the genome FASTA at its stated size (--big-genome-bytes,
     default 50e9 B): generated into host memory, encoded with the segmented
@@ -290,6 +325,39 @@ def big_genome_leg(args, dev):
                "encode_MB_per_s": round(N / enc_s / 1e6, 1), "upload_s": round(up_s, 1)}
         log("big genome: %d windows of %d GiB, %.1f GB/s sustained, closure amplification %.4f"
             % (windows, win >> 30, rec["GB_per_s"], rec["closure_amplification"]))
+        # coordinate access (chr:start-end) through the .fai-style index
+        t0 = time.time()
+        fidx = lz.fasta_index(x)
+        idx_s = time.time() - t0
+        lat, nbases = [], 0
+        rscr = torch.empty((1 << 21) + arc.scratch_bytes(1, 4096), dtype=torch.uint8, device=dev)
+        rout = torch.empty(1 << 20, dtype=torch.uint8, device=dev)
+        for q in range(220):
+            sq = fidx[int(rng.integers(0, len(fidx)))]
+            L = int(rng.integers(1000, 100_000))
+            s0 = int(rng.integers(0, int(sq.length) - L))
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            got = arc.decode_region(sq, s0, s0 + L, out=rout, scratch=rscr)
+            e1.record(stream)
+            e1.synchronize()
+            if q >= 20:
+                lat.append(e0.elapsed_time(e1) * 1e3)
+                nbases += L
+            if q < 20:       # checked against the source by line arithmetic
+                W, LB = int(sq.line_bases), int(sq.line_bytes)
+                k = np.arange(s0, s0 + L)
+                want = x[int(sq.offset) + (k // W) * LB + k % W]
+                if not np.array_equal(got.cpu().numpy(), want):
+                    raise RuntimeError("region %s:%d-%d differs from the source" % (sq.name, s0, s0 + L))
+        arc.sync_status()
+        rec["regions"] = {"n": len(lat), "bases": "1 kb..100 kb", "device_p50_us": pct(lat, 50),
+                          "device_p99_us": pct(lat, 99), "index_s": round(idx_s, 2),
+                          "what": "lz_decode_region: chr:start-end through a .fai-style index, "
+                                  "range decode with closure, newlines removed on the device"}
+        log("big genome regions: %s" % rec["regions"])
+        del rscr, rout
         del out, scr, vscr, arc
         torch.cuda.empty_cache()
         return rec
@@ -378,7 +446,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--bytes", type=int, default=1 << 30, help="FASTQ size (default 1 GiB)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", choices=("all", "decode", "copy", "serve", "genome", "biggenome"), default="all",
+    ap.add_argument("--legs", choices=("all", "decode", "copy", "serve", "genome", "biggenome", "reads"),
+                    default="all",
                     help="decode: only the whole-file decode in the reported launch mode "
                          "(for profiling; no range leg, no CPU baseline); copy: a plain "
                          "device-to-device copy of --bytes bytes (counter calibration)")
@@ -492,6 +561,9 @@ def main() -> int:
 
     if args.legs == "serve":
         return serve_leg(args, arc, x, starts)
+    if args.legs == "reads":        # single-read latency only (for kernel traces)
+        print(json.dumps({"read_access_us": read_latency(arc, starts, 200, dev)}), flush=True)
+        return 0
     # both launch modes: one launch per dependency level, and one persistent
     # launch whose workgroups wait on per-block completion flags
     modes = {}
@@ -542,6 +614,12 @@ def main() -> int:
         arc.sync_status()
         range_gbps = N * r_steps / (r0.elapsed_time(r1) / 1e3) / 1e9
         log("windowed range decode (256 MiB window): %.1f GB/s" % range_gbps)
+
+    e2e = None
+    if args.legs == "all":
+        e2e = end_to_end(arc, a, N, dev)
+        log("end-to-end with PCIe: %s" % e2e)
+        arc.set_tuning(sync_mode=best, wg_per_cu=3)
 
     big = None
     if args.legs == "all" and args.big_genome_bytes:
@@ -624,6 +702,7 @@ def main() -> int:
         "range_window": "whole file as consecutive 256 MiB lz_decode_range windows, bit-exact",
         "read_access_us": read_lat,
         "range_genome": big,
+        "end_to_end_pcie": e2e,
         "batched_lookups": batch_res,
         "encode_s": round(enc_s, 1),
     }

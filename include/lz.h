@@ -181,6 +181,35 @@ int lz_read_lookup(lz_handle* h, const int64_t* d_ids, uint64_t n, uint8_t* d_ou
 int lz_read_lookup_noalloc(lz_handle* h, const int64_t* d_ids, uint64_t n, uint8_t* d_out,
                            uint64_t cap, uint64_t* d_offsets, hipStream_t s);
 
+/* ---- FASTA coordinate access (chr:pos) ----------------------------------
+ * The paper leaves coordinate-based access to FASTA as future work (Read-Level
+ * Index subsection).  A sequence of a FASTA file is described as in a .fai
+ * index: byte offset of its first base, number of bases, bases per full line
+ * and bytes per full line (bases + newline).  Base k of the sequence then lies
+ * at byte offset + (k / line_bases) * line_bytes + k % line_bases. */
+typedef struct lz_fasta_seq {
+  char name[64];          /* NUL-terminated, truncated to 63 bytes            */
+  uint64_t offset;        /* byte offset of the first base                     */
+  uint64_t length;        /* bases                                            */
+  uint32_t line_bases;    /* bases per full line (0 if the lines are uneven)  */
+  uint32_t line_bytes;    /* bytes per full line                              */
+} lz_fasta_seq;
+
+/* Host: scan a FASTA text (records '>' name line, then sequence lines ending
+ * in '\n') and describe its sequences; writes min(count, cap) entries, *count
+ * receives the total.  EINVAL if the text does not start with '>'. */
+int lz_fasta_index(const uint8_t* src, uint64_t n, lz_fasta_seq* out, uint64_t cap,
+                   uint64_t* count);
+
+/* Device: d_out[0 .. end-start) = bases [start, end) of sequence *sq (no
+ * newlines): the covering byte range is decoded with lz_decode_range into the
+ * front of d_scratch, then the bases are gathered by line arithmetic.
+ * ERANGE if end > sq->length or start > end; ENOINDEX if the sequence's lines
+ * are uneven (line_bases 0).  d_scratch needs the covering byte range rounded
+ * up to 256 bytes plus the scratch of a range decode. */
+int lz_decode_region(lz_handle* h, const lz_fasta_seq* sq, uint64_t start, uint64_t end,
+                     uint8_t* d_out, void* d_scratch, uint64_t scratch_len, hipStream_t s);
+
 /* Batched requests (mixed reads and ranges) resolved together: one closure
  * over all requests, one decode launch over the shared level-ordered queue,
  * then a gather into d_out at d_offsets (device, n+1 entries).  d_reqs is a

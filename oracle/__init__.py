@@ -226,3 +226,30 @@ def rans_decode(body: bytes, n: int, n_words: int, freq, prob_bits: int, lanes: 
                                C.c_uint32(prob_bits), C.c_uint32(lanes),
                                C.c_void_p(o.ctypes.data))
     return rc, (o[:n].tobytes() if rc == 0 else None)
+
+
+def fasta_sequences(text: bytes) -> dict:
+    """Plain definition of a FASTA file's sequences: a record is a '>' line
+    whose name is the text up to the first space or tab, followed by lines
+    whose concatenation (newlines removed) is the sequence.  Returns
+    {name: (sequence bytes, byte offset of its first base)}."""
+    out = {}
+    pos = 0
+    for rec in text.split(b"\n>"):
+        start = pos
+        pos += len(rec) + 2                    # the "\n>" separator
+        if start == 0:
+            assert rec.startswith(b">")
+            rec = rec[1:]
+            start = 1
+        head, _, body = rec.partition(b"\n")
+        name = head.split(b" ")[0].split(b"\t")[0].decode()
+        out[name] = (body.replace(b"\n", b""), start + len(head) + 1)
+    return out
+
+
+def fasta_region(text: bytes, name: str, start: int, end: int) -> bytes:
+    """Bases [start, end) of sequence `name` (plain definition: slice of the
+    concatenated sequence lines); the coordinate access the paper names as
+    future work in its Read-Level Index subsection."""
+    return fasta_sequences(text)[name][0][start:end]

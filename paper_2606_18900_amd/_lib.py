@@ -20,7 +20,7 @@ NAMES = {0: "LZ_OK", -1: "LZ_EINVAL", -2: "LZ_EFORMAT", -3: "LZ_ECAPACITY", -4: 
 # every symbol include/lz.h declares
 EXPORTS = ["lz_params_default", "lz_encode", "lz_free", "lz_info_get", "lz_open", "lz_close",
            "lz_get_info", "lz_set_tuning", "lz_get_tuning", "lz_decode_all", "lz_decode_range",
-           "lz_read_lookup", "lz_read_lookup_noalloc", "lz_decode_batch", "lz_verify", "lz_verify_range", "lz_last_stats", "lz_sync_status", "lz_last_error"]
+           "lz_read_lookup", "lz_read_lookup_noalloc", "lz_fasta_index", "lz_decode_region", "lz_decode_batch", "lz_verify", "lz_verify_range", "lz_last_stats", "lz_sync_status", "lz_last_error"]
 
 
 class LzError(RuntimeError):
@@ -57,6 +57,11 @@ class Stats(C.Structure):
     _fields_ = [("closure_blocks", C.c_uint64), ("scratch_slots", C.c_uint64), ("covering", C.c_uint64)]
 
 
+class FastaSeq(C.Structure):
+    _fields_ = [("name", C.c_char * 64), ("offset", C.c_uint64), ("length", C.c_uint64),
+                ("line_bases", C.c_uint32), ("line_bytes", C.c_uint32)]
+
+
 class Tuning(C.Structure):
     _fields_ = [("sync_mode", C.c_uint32), ("wg_per_cu", C.c_uint32), ("spin_limit", C.c_uint32)]
 
@@ -84,6 +89,8 @@ def lib():
         L.lz_decode_range.argtypes = [vp, u64, u64, vp, vp, u64, vp]
         L.lz_read_lookup.argtypes = [vp, vp, u64, vp, u64, vp, vp, u64, vp]
         L.lz_read_lookup_noalloc.argtypes = [vp, vp, u64, vp, u64, vp, vp]
+        L.lz_fasta_index.argtypes = [vp, u64, vp, u64, vp]
+        L.lz_decode_region.argtypes = [vp, vp, u64, u64, vp, vp, u64, vp]
         L.lz_decode_batch.argtypes = [vp, vp, vp, u64, vp, u64, vp, vp, u64, vp]
         L.lz_verify.argtypes = [vp, vp, vp, vp, u64, vp]
         L.lz_verify_range.argtypes = [vp, vp, u64, u64, vp, u64, vp]

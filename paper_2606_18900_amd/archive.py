@@ -32,6 +32,18 @@ def encode(data, **params) -> bytes:
         lib().lz_free(out)
 
 
+def fasta_index(data) -> list:
+    """lz_fasta_index: .fai-style description (name, offset, length, line
+    widths) of every sequence of a FASTA text, for lz_decode_region."""
+    a = np.frombuffer(memoryview(data), dtype=np.uint8) if not isinstance(data, np.ndarray) else data
+    cnt = C.c_uint64()
+    check(lib().lz_fasta_index(C.c_void_p(a.ctypes.data if a.size else 0), a.size, None, 0, C.byref(cnt)))
+    arr = (_lib.FastaSeq * max(1, cnt.value))()
+    check(lib().lz_fasta_index(C.c_void_p(a.ctypes.data if a.size else 0), a.size, arr, cnt.value,
+                               C.byref(cnt)))
+    return list(arr[: cnt.value])
+
+
 def info(archive: bytes) -> _lib.Info:
     i = _lib.Info()
     a = np.frombuffer(memoryview(archive), dtype=np.uint8)
@@ -173,6 +185,22 @@ class Archive:
         check(lib().lz_read_lookup_noalloc(self.h, _ptr(ids), ids.numel(), _ptr(out), out.numel(),
                                            _ptr(offsets), _stream(stream)))
         return out, offsets
+
+    def decode_region(self, seq: _lib.FastaSeq, start: int, end: int, out: torch.Tensor | None = None,
+                      scratch: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """lz_decode_region: bases [start, end) of FASTA sequence `seq` (an
+        entry of fasta_index), newlines removed."""
+        n = end - start
+        if out is None:
+            out = torch.empty(max(n, 1), dtype=torch.uint8, device=self.device)
+        if scratch is None:
+            W = max(1, int(seq.line_bases))
+            span = n + n // W + 2
+            scratch = torch.empty(((span + 255) & ~255) + self.scratch_bytes(1, 4096), dtype=torch.uint8,
+                                  device=self.device)
+        check(lib().lz_decode_region(self.h, C.byref(seq), start, end, _ptr(out), _ptr(scratch),
+                                     scratch.numel(), _stream(stream)))
+        return out[:n]
 
     def decode_batch(self, reqs: torch.Tensor, n: torch.Tensor, n_max: int, out: torch.Tensor,
                      offsets: torch.Tensor, scratch: torch.Tensor, stream=None):

@@ -847,3 +847,73 @@ extern "C" int lz_encode(const uint8_t* x, uint64_t n, const lz_params* pp, uint
   *archive_len = total;
   return LZ_OK;
 }
+
+// .fai-style description of the sequences of a FASTA text.  Record starts
+// ('>' at the start of a line) are found first; then each sequence's lines
+// are checked in parallel chunks: with W the length of its first line, every
+// newline but the sequence's last must lie at offset + W + k (W + 1).
+extern "C" int lz_fasta_index(const uint8_t* x, uint64_t n, lz_fasta_seq* out, uint64_t cap,
+                              uint64_t* count) {
+  if (!count || (n && !x) || (cap && !out)) return lz_fail(LZ_EINVAL, "lz_fasta_index: null argument");
+  *count = 0;
+  if (!n) return LZ_OK;
+  if (x[0] != '>') return lz_fail(LZ_EINVAL, "lz_fasta_index: text does not start with '>'");
+  std::vector<uint64_t> starts;
+  for (uint64_t p = 0; p < n;) {
+    const uint8_t* g = (const uint8_t*)std::memchr(x + p, '>', (size_t)(n - p));
+    if (!g) break;
+    const uint64_t q = (uint64_t)(g - x);
+    if (q == 0 || x[q - 1] == '\n') starts.push_back(q);
+    p = q + 1;
+  }
+  starts.push_back(n);
+  const unsigned threads = std::max(1u, std::thread::hardware_concurrency());
+  for (size_t r = 0; r + 1 < starts.size(); r++) {
+    const uint64_t h0 = starts[r], end = starts[r + 1];
+    const uint8_t* nl = (const uint8_t*)std::memchr(x + h0, '\n', (size_t)(end - h0));
+    const uint64_t he = nl ? (uint64_t)(nl - x) : end;
+    lz_fasta_seq sq;
+    std::memset(&sq, 0, sizeof(sq));
+    uint64_t q = h0 + 1, j = 0;
+    while (q < he && x[q] != ' ' && x[q] != '\t' && x[q] != '\r') {
+      if (j < sizeof(sq.name) - 1) sq.name[j++] = (char)x[q];
+      q++;
+    }
+    const uint64_t a = std::min(he + 1, end);
+    sq.offset = a;
+    // first line width, then the other newlines on the grid, in chunks
+    const uint8_t* f = (const uint8_t*)std::memchr(x + a, '\n', (size_t)(end - a));
+    const uint64_t W = f ? (uint64_t)(f - x) - a : end - a;
+    const uint64_t last_nl = (end > a && x[end - 1] == '\n') ? end - 1 : end;   // the sequence's last newline
+    const uint64_t chunk = 64ull << 20, nch = (end - a + chunk - 1) / chunk;
+    std::vector<uint64_t> nls(nch ? nch : 1, 0);
+    std::vector<uint8_t> bad(nch ? nch : 1, 0);
+    parallel_for(nch, threads, [&](uint64_t c, unsigned) {
+      const uint64_t c0 = a + c * chunk, c1 = std::min(end, c0 + chunk);
+      uint64_t cnt = 0;
+      for (uint64_t p = c0; p < c1;) {
+        const uint8_t* l = (const uint8_t*)std::memchr(x + p, '\n', (size_t)(c1 - p));
+        if (!l) break;
+        const uint64_t e = (uint64_t)(l - x);
+        cnt++;
+        if (e != last_nl && (e < a + W || (e - a - W) % (W + 1))) bad[c] = 1;
+        p = e + 1;
+      }
+      nls[c] = cnt;
+    });
+    uint64_t newlines = 0;
+    bool even = W > 0;
+    for (uint64_t c = 0; c < nch; c++) { newlines += nls[c]; if (bad[c]) even = false; }
+    sq.length = (end - a) - newlines;
+    if (even && last_nl == end - 1 && end - 1 > a) {          // last line: 1..W bases
+      const uint64_t full = (last_nl - a) / (W + 1), rem = (last_nl - a) - full * (W + 1);
+      if (rem > W || (rem == 0 && full == 0)) even = false;
+    }
+    if (last_nl != end - 1) even = false;                    // text must end its lines with '\n'
+    sq.line_bases = even ? (uint32_t)W : 0;
+    sq.line_bytes = even ? (uint32_t)(W + 1) : 0;
+    if (r < cap) out[r] = sq;
+  }
+  *count = starts.size() - 1;
+  return LZ_OK;
+}

@@ -971,28 +971,30 @@ __device__ void load_tables(Smem& S, const DevArgs& A) {
 __global__ void __launch_bounds__(kWG, 3) k_decode(DevArgs A) {   // 3 waves per SIMD: at most 168 VGPRs
   __shared__ Smem S;
   const uint32_t t = threadIdx.x;
-  load_tables(S, A);
-#ifdef LZ_STAGE_CLOCKS
-  if (t < kClkSlots) S.clk[t] = 0;
-#endif
-  __syncthreads();
-  const uint32_t epoch = __hip_atomic_load(A.ctl + kCtlEpoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   uint32_t qb = A.q_begin, qe = A.q_end;
   if (A.qptr) {
     qb = A.qptr[A.q_begin];
     qe = A.qptr[A.q_end];
   }
   // blocks of this workgroup: a grid-stride slice of the queue (per-level
-  // launches) or tickets in queue order (persistent launch)
-  uint32_t it = qb + blockIdx.x;
-  for (;;) {
-    if (A.persistent) {
-      if (t == 0) S.item = qb + atomicAdd(A.ctl + kCtlTicket, 1u);
-      __syncthreads();
-      it = S.item;
-      __syncthreads();
-    }
-    if (it >= qe) break;
+  // launches) or tickets in queue order (persistent launch); a workgroup
+  // without a block leaves before loading any table
+  auto ticket = [&]() -> uint32_t {
+    if (t == 0) S.item = qb + atomicAdd(A.ctl + kCtlTicket, 1u);
+    __syncthreads();
+    const uint32_t v = S.item;
+    __syncthreads();
+    return v;
+  };
+  uint32_t it = A.persistent ? ticket() : qb + blockIdx.x;
+  if (it >= qe) return;
+  load_tables(S, A);
+#ifdef LZ_STAGE_CLOCKS
+  if (t < kClkSlots) S.clk[t] = 0;
+#endif
+  __syncthreads();
+  const uint32_t epoch = __hip_atomic_load(A.ctl + kCtlEpoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  while (it < qe) {
     const uint32_t b = A.queue[it];
     if (A.persistent) {
       // wait for every dependency's completion flag, then acquire
@@ -1018,6 +1020,7 @@ __global__ void __launch_bounds__(kWG, 3) k_decode(DevArgs A) {   // 3 waves per
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       __syncthreads();
       if (t == 0) __hip_atomic_store(A.flags + b, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      it = ticket();
     } else {
       __syncthreads();
       it += gridDim.x;
@@ -1194,6 +1197,30 @@ int lz_launch_verify(lz_handle* h, const uint8_t* d_out, uint64_t b0, uint64_t n
   }
   if (d_tree) hipLaunchKernelGGL(k_fnv_tree, dim3(1), dim3(1), 0, s, hashes, nb, d_tree);
   return launch_ok("lz_verify");
+}
+
+// ---- FASTA regions: bases of a sequence gathered from its decoded bytes -------
+namespace {
+
+// out[i] = base start + i of a sequence whose first base is at byte `offset`
+// of the file, W bases per line of LB bytes; tmp holds the file bytes from
+// `first` on.
+__global__ void k_region_gather(const uint8_t* tmp, uint64_t first, uint64_t offset, uint64_t start,
+                                uint64_t nb, uint32_t W, uint32_t LB, uint8_t* out) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nb;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = start + i;
+    out[i] = tmp[offset + (k / W) * LB + k % W - first];
+  }
+}
+
+}  // namespace
+
+int lz_launch_region_gather(const uint8_t* tmp, uint64_t first, uint64_t offset, uint64_t start,
+                            uint64_t nb, uint32_t W, uint32_t LB, uint8_t* out, hipStream_t s) {
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(4096, (nb + 255) / 256);
+  hipLaunchKernelGGL(k_region_gather, dim3(grid), dim3(256), 0, s, tmp, first, offset, start, nb, W, LB, out);
+  return launch_ok("lz_decode_region");
 }
 
 // ---- requests: ranges, read lookups, batches --------------------------------

@@ -31,6 +31,8 @@ int lz_launch_decode_all(lz_handle* h, uint8_t* out, hipStream_t s);
 int lz_launch_verify(lz_handle* h, const uint8_t* d_out, uint64_t b0, uint64_t nb, uint64_t* d_tree,
                      void* scratch, hipStream_t s);
 int lz_noalloc_setup(int dev, void** ptr);
+int lz_launch_region_gather(const uint8_t* tmp, uint64_t first, uint64_t offset, uint64_t start,
+                            uint64_t nb, uint32_t W, uint32_t LB, uint8_t* out, hipStream_t s);
 int lz_launch_requests(lz_handle* h, const lz_request* d_reqs, const uint32_t* d_n, uint64_t n_max,
                        uint64_t single_off, uint64_t single_len, const int64_t* d_ids,
                        uint8_t* d_out, uint64_t cap, uint64_t* d_offsets, void* d_scratch,
@@ -418,4 +420,24 @@ extern "C" int lz_decode_batch(lz_handle* h, const lz_request* d_reqs, const uin
   if (!h || !d_reqs || !d_n || !d_out || !d_offsets) return lz_fail(LZ_EINVAL, "lz_decode_batch: null argument");
   if (!n_max) return LZ_OK;
   return lz_launch_requests(h, d_reqs, d_n, n_max, 0, 0, nullptr, d_out, cap, d_offsets, d_scratch, scratch_len, s);
+}
+
+extern "C" int lz_decode_region(lz_handle* h, const lz_fasta_seq* sq, uint64_t start, uint64_t end,
+                                uint8_t* d_out, void* d_scratch, uint64_t scratch_len, hipStream_t s) {
+  if (!h || !sq) return lz_fail(LZ_EINVAL, "lz_decode_region: null argument");
+  if (start > end || end > sq->length) return lz_fail(LZ_ERANGE, "lz_decode_region: [%llu, %llu) outside the sequence of %llu bases", (unsigned long long)start, (unsigned long long)end, (unsigned long long)sq->length);
+  if (!sq->line_bases || sq->line_bytes != sq->line_bases + 1u)
+    return lz_fail(LZ_ENOINDEX, "lz_decode_region: sequence has uneven lines");
+  if (start == end) return LZ_OK;
+  if (!d_out || !d_scratch) return lz_fail(LZ_EINVAL, "lz_decode_region: null buffer");
+  const uint64_t W = sq->line_bases, LB = sq->line_bytes;
+  auto pos = [&](uint64_t k) { return sq->offset + (k / W) * LB + k % W; };
+  const uint64_t first = pos(start), last = pos(end - 1) + 1;
+  if (last > h->av.n) return lz_fail(LZ_ERANGE, "lz_decode_region: sequence lies outside the file");
+  const uint64_t span = last - first, head = (span + 255) & ~255ull;
+  if (((uintptr_t)d_scratch & 255) || scratch_len < head) return lz_fail(LZ_ECAPACITY, "lz_decode_region: scratch needs more than %llu bytes", (unsigned long long)head);
+  uint8_t* tmp = reinterpret_cast<uint8_t*>(d_scratch);
+  int rc = lz_decode_range(h, first, span, tmp, tmp + head, scratch_len - head, s);
+  if (rc) return rc;
+  return lz_launch_region_gather(tmp, first, sq->offset, start, end - start, (uint32_t)W, (uint32_t)LB, d_out, s);
 }
