@@ -968,63 +968,77 @@ __device__ void load_tables(Smem& S, const DevArgs& A) {
   }
 }
 
+// Grid-wide barrier of a cooperative launch: arrivals are counted in one
+// control word (reset before the launch); barrier k (k = 1, 2, ...) completes
+// when nwg * k workgroups have arrived.  Agent-scope release before the
+// arrival and acquire after the wait make the blocks decoded before the
+// barrier visible to every workgroup after it.  A wait longer than the spin
+// limit latches the watchdog and lets the kernel finish (status ECORRUPT).
+__device__ void grid_barrier(uint32_t* ctl, uint32_t target, uint32_t spin_limit) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(ctl + kCtlTicket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t seen;
+    for (uint32_t spins = 0;
+         (seen = __hip_atomic_load(ctl + kCtlTicket, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < target; spins++) {
+      if (spins >= spin_limit || ((spins & 255u) == 255u && watchdog_fired(ctl))) {
+        watchdog(ctl, 4, target, 0, seen, target);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+// Per-level launches: a grid-stride slice of the level's queue; a workgroup
+// without a block leaves before loading any table.  Persistent (one
+// cooperative launch, every workgroup resident): the levels in order, each a
+// grid-stride slice of qptr[L] .. qptr[L+1], a grid barrier before every
+// non-empty level but the first.  decode_block has one call site, so the
+// kernel's register budget is that of one copy of it.
 __global__ void __launch_bounds__(kWG, 3) k_decode(DevArgs A) {   // 3 waves per SIMD: at most 168 VGPRs
   __shared__ Smem S;
   const uint32_t t = threadIdx.x;
-  uint32_t qb = A.q_begin, qe = A.q_end;
-  if (A.qptr) {
-    qb = A.qptr[A.q_begin];
-    qe = A.qptr[A.q_end];
+  uint32_t it = 0, qe = 0, L = 0, bars = 0;
+  bool pending = false;       // (persistent) a non-empty level has been started
+  if (!A.persistent) {
+    uint32_t qb = A.q_begin;
+    qe = A.q_end;
+    if (A.qptr) {
+      qb = A.qptr[A.q_begin];
+      qe = A.qptr[A.q_end];
+    }
+    it = qb + blockIdx.x;
+    if (it >= qe) return;
   }
-  // blocks of this workgroup: a grid-stride slice of the queue (per-level
-  // launches) or tickets in queue order (persistent launch); a workgroup
-  // without a block leaves before loading any table
-  auto ticket = [&]() -> uint32_t {
-    if (t == 0) S.item = qb + atomicAdd(A.ctl + kCtlTicket, 1u);
-    __syncthreads();
-    const uint32_t v = S.item;
-    __syncthreads();
-    return v;
-  };
-  uint32_t it = A.persistent ? ticket() : qb + blockIdx.x;
-  if (it >= qe) return;
-  load_tables(S, A);
 #ifdef LZ_STAGE_CLOCKS
   if (t < kClkSlots) S.clk[t] = 0;
 #endif
-  __syncthreads();
-  const uint32_t epoch = __hip_atomic_load(A.ctl + kCtlEpoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  while (it < qe) {
-    const uint32_t b = A.queue[it];
+  bool tables = false;        // tables are loaded before the workgroup's first block
+  for (;;) {
     if (A.persistent) {
-      // wait for every dependency's completion flag, then acquire
-      const uint64_t d0 = ld64(A.arc + A.off_dep_ptr + 8ull * b);
-      const uint64_t d1 = ld64(A.arc + A.off_dep_ptr + 8ull * (b + 1));
-      for (uint64_t k = d0 + t; k < d1; k += kWG) {
-        const uint32_t d = ld32(A.arc + A.off_dep_idx + 4 * k);
-        uint32_t f;
-        for (uint32_t spins = 0;
-             (f = __hip_atomic_load(A.flags + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != epoch; spins++) {
-          if (spins >= A.spin_limit || ((spins & 255u) == 255u && watchdog_fired(A.ctl))) {
-            watchdog(A.ctl, 1, b, d, f, epoch);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
+      while (it >= qe && L < kMaxLevels) {     // this workgroup's next block, in a later level
+        const uint32_t b0 = A.qptr[L], b1 = A.qptr[L + 1];
+        L++;
+        if (b0 >= b1) continue;
+        if (pending) grid_barrier(A.ctl, gridDim.x * ++bars, A.spin_limit);
+        pending = true;
+        it = b0 + blockIdx.x;
+        qe = b1;
       }
-      __syncthreads();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    decode_block(S, A, b);
-    if (A.persistent) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (it >= qe) break;
+    if (!tables) {
+      load_tables(S, A);
       __syncthreads();
-      if (t == 0) __hip_atomic_store(A.flags + b, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      it = ticket();
-    } else {
-      __syncthreads();
-      it += gridDim.x;
+      tables = true;
     }
+    decode_block(S, A, A.queue[it]);
+    __syncthreads();
+    it += gridDim.x;
   }
 #ifdef LZ_STAGE_CLOCKS
   __syncthreads();
@@ -1077,6 +1091,15 @@ __global__ void k_begin(uint32_t* ctl) {
 
 size_t lz_decode_smem_bytes() { return sizeof(Smem); }
 
+// Decode workgroups resident per compute unit (the cooperative grid is this
+// times the CU count).
+int lz_decode_occupancy(int* per_cu) {
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, reinterpret_cast<const void*>(k_decode),
+                                                                    (int)kWG, 0);
+  if (e != hipSuccess) return lz_fail(LZ_EDEVICE, "decode occupancy: %s", hipGetErrorString(e));
+  return LZ_OK;
+}
+
 static DevArgs make_args(const lz_handle* h) {
   DevArgs A{};
   const ArchiveView& v = h->av;
@@ -1118,6 +1141,23 @@ int lz_launch_setup(lz_handle* h, hipStream_t s) {
   return launch_ok("lz_open setup kernels");
 }
 
+// Persistent mode: one cooperative launch of every resident workgroup (the
+// runtime refuses it rather than leave any workgroup waiting for a slot).
+// Inside a stream capture the levels are launched one by one instead.
+static int launch_persistent(lz_handle* h, DevArgs A, hipStream_t s, bool* done) {
+  *done = false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) return lz_fail(LZ_EDEVICE, "stream capture query failed");
+  if (cs != hipStreamCaptureStatusNone) return LZ_OK;
+  A.persistent = 1;
+  void* args[] = {&A};
+  const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_decode), dim3(h->coop_grid),
+                                                  dim3(kWG), args, 0, s);
+  if (e != hipSuccess) return lz_fail(LZ_EDEVICE, "cooperative decode launch: %s", hipGetErrorString(e));
+  *done = true;
+  return LZ_OK;
+}
+
 int lz_launch_decode_all(lz_handle* h, uint8_t* out, hipStream_t s) {
   DevArgs A = make_args(h);
   A.queue = h->ws.queue;
@@ -1126,22 +1166,20 @@ int lz_launch_decode_all(lz_handle* h, uint8_t* out, hipStream_t s) {
   const uint32_t slots = (uint32_t)(h->n_cu * std::max(1u, h->tune.wg_per_cu));
   hipLaunchKernelGGL(k_begin, dim3(1), dim3(1), 0, s, h->ws.ctl);
   if (h->tune.sync_mode == 1) {
-    A.persistent = 1;
-    A.q_begin = 0;
-    A.q_end = (uint32_t)h->av.n_blocks;
-    const uint32_t grid = (uint32_t)std::min<uint64_t>(slots, std::max<uint64_t>(1, h->av.n_blocks));
-    hipLaunchKernelGGL(k_decode, dim3(grid), dim3(kWG), smem, s, A);
-  } else {
-    uint32_t base = 0;
-    for (uint32_t L = 0; L < h->av.n_levels; L++) {
-      const uint32_t c = h->level_count[L];
-      if (c) {
-        A.q_begin = base;
-        A.q_end = base + c;
-        hipLaunchKernelGGL(k_decode, dim3(std::min(c, slots)), dim3(kWG), smem, s, A);
-      }
-      base += c;
+    A.qptr = h->ws.level_ptr;
+    bool done = false;
+    const int rc = launch_persistent(h, A, s, &done);
+    if (rc || done) return rc ? rc : launch_ok("lz_decode_all");
+  }
+  uint32_t base = 0;
+  for (uint32_t L = 0; L < h->av.n_levels; L++) {
+    const uint32_t c = h->level_count[L];
+    if (c) {
+      A.q_begin = base;
+      A.q_end = base + c;
+      hipLaunchKernelGGL(k_decode, dim3(std::min(c, slots)), dim3(kWG), smem, s, A);
     }
+    base += c;
   }
   return launch_ok("lz_decode_all");
 }
@@ -1595,7 +1633,7 @@ int lz_launch_requests(lz_handle* h, const lz_request* d_reqs, const uint32_t* d
   hipLaunchKernelGGL(k_req_levels, dim3(g_wide), dim3(256), 0, s, R);
   hipLaunchKernelGGL(k_req_level_scan, dim3(1), dim3(64), 0, s, R);
   hipLaunchKernelGGL(k_req_scatter, dim3(g_wide), dim3(256), 0, s, R);
-  // decode the closure in level order (persistent, or one launch per level)
+  // decode the closure in level order (one cooperative launch, or one launch per level)
   DevArgs A = make_args(h);
   A.queue = h->ws.rqueue;
   A.qptr = h->ws.rlevel_ptr;
@@ -1603,12 +1641,12 @@ int lz_launch_requests(lz_handle* h, const lz_request* d_reqs, const uint32_t* d
   A.out = d_out;
   const uint32_t slots = (uint32_t)(h->n_cu * std::max(1u, h->tune.wg_per_cu));
   const uint32_t grid = (uint32_t)std::min<uint64_t>(slots, std::max<uint64_t>(1, v.n_blocks));
+  bool done = false;
   if (h->tune.sync_mode == 1) {
-    A.persistent = 1;
-    A.q_begin = 0;
-    A.q_end = 64;
-    hipLaunchKernelGGL(k_decode, dim3(grid), dim3(kWG), 0, s, A);
-  } else {
+    const int rc = launch_persistent(h, A, s, &done);
+    if (rc) return rc;
+  }
+  if (!done) {
     for (uint32_t L = 0; L < v.n_levels; L++) {
       A.q_begin = L;
       A.q_end = L + 1;

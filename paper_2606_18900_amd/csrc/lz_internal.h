@@ -61,7 +61,7 @@ struct Workspace {
 // control words in Workspace::ctl (u32 each; 64-bit values use two words)
 enum : uint32_t {
   kCtlStatus = 0,     // latched status bits
-  kCtlTicket = 1,     // persistent-kernel ticket counter
+  kCtlTicket = 1,     // cooperative decode: grid-barrier arrivals
   kCtlEpoch = 2,      // completion epoch (per-block flags)
   kCtlREpoch = 3,     // request epoch (closure marks)
   kCtlListTail = 4,   // closure list: entries pushed
@@ -83,6 +83,7 @@ struct lz_handle {
   lz_tuning tune;
   int n_cu;
   int dev;                            // device the handle was opened on
+  uint32_t coop_grid;                 // resident decode workgroups (cooperative launch)
   uint32_t level_count[kMaxLevels];   // host copy of the whole-file level histogram
   uint64_t literal_bytes;             // sum of n_lit over blocks
   uint64_t payload_bytes;             // end of the last block payload

@@ -31,6 +31,7 @@ int lz_launch_decode_all(lz_handle* h, uint8_t* out, hipStream_t s);
 int lz_launch_verify(lz_handle* h, const uint8_t* d_out, uint64_t b0, uint64_t nb, uint64_t* d_tree,
                      void* scratch, hipStream_t s);
 int lz_noalloc_setup(int dev, void** ptr);
+int lz_decode_occupancy(int* per_cu);
 int lz_launch_region_gather(const uint8_t* tmp, uint64_t first, uint64_t offset, uint64_t start,
                             uint64_t nb, uint32_t W, uint32_t LB, uint8_t* out, hipStream_t s);
 int lz_launch_requests(lz_handle* h, const lz_request* d_reqs, const uint32_t* d_n, uint64_t n_max,
@@ -273,6 +274,11 @@ extern "C" int lz_open(const uint8_t* d_archive, uint64_t len, void* d_ws, uint6
   if (rc) { delete h; return rc; }
   h->n_cu = prop.multiProcessorCount;
   h->dev = dev;
+  {
+    int per_cu = 0;
+    if ((rc = lz_decode_occupancy(&per_cu))) { delete h; return rc; }
+    h->coop_grid = (uint32_t)std::max(1, std::min(per_cu, 3) * h->n_cu);
+  }
   {
     void* p = nullptr;   // resolve this device's allocation-free scratch once
     if ((rc = lz_noalloc_setup(dev, &p))) { delete h; return rc; }
