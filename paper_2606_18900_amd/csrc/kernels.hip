@@ -1554,6 +1554,187 @@ __global__ void k_req_scatter(ReqArgs R) {
   }
 }
 
+// Plan of a small request call in one workgroup of 1024 threads, the same
+// steps as k_req_begin .. k_req_scatter without launches between them: clear
+// the previous closure's addresses, spans and prefix sums of the requests,
+// covering blocks marked and listed, the dependency closure expanded round by
+// round (a round takes every listed entry not yet expanded; a block joins the
+// list once, when its mark is raised to this call's epoch), then a counting
+// sort of the closure by level with each block's address.
+constexpr uint32_t kPlanWG = 1024;
+
+__global__ void __launch_bounds__(kPlanWG) k_req_plan(ReqArgs R) {
+  __shared__ uint64_t wsum[2][kPlanWG / 64];
+  __shared__ uint32_t lvl_cnt[64], lvl_cur[64];
+  __shared__ uint32_t s_tail, s_slots, s_nreq, s_epoch;
+  __shared__ uint64_t s_pairs;
+  const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  // begin: the previous call's closure loses its addresses; new epochs
+  {
+    const uint32_t prev = min(R.ctl[kCtlListTail], (uint32_t)R.n_blocks);
+    for (uint32_t i = t; i < prev; i += kPlanWG) {
+      const uint32_t b = (uint32_t)R.list[i];
+      if (b < R.n_blocks) R.addr[b] = 0;
+    }
+  }
+  if (t < 64) lvl_cnt[t] = 0;
+  if (t == 0) {
+    uint64_t n = R.n_max;
+    if (R.mode == 2) n = min((uint64_t)*R.d_n, R.n_max);
+    s_nreq = (uint32_t)n;
+    s_tail = 0;
+    s_slots = 0;
+  }
+  __syncthreads();
+  if (t == 0) {
+    s_epoch = R.ctl[kCtlREpoch] + 1;
+    R.ctl[kCtlREpoch] = s_epoch;
+    R.ctl[kCtlEpoch] += 1;
+    R.ctl[kCtlTicket] = 0;
+    R.ctl[kCtlListHead] = 0;
+    R.ctl[kCtlListDone] = 0;
+    R.ctl[kCtlNReq] = s_nreq;
+  }
+  __syncthreads();
+  const uint32_t epoch = s_epoch;
+  const uint32_t nreq = s_nreq;
+  // spans, output offsets and covering-block counts, 1024 requests a round
+  uint64_t carry_len = 0, carry_cnt = 0;
+  for (uint32_t c0 = 0; c0 < nreq; c0 += kPlanWG) {
+    const uint32_t j = c0 + t;
+    uint64_t s0 = 0, e0 = 0;
+    if (j < nreq) {
+      bool ok = true;
+      if (R.mode == 0) {
+        s0 = R.a0;
+        e0 = R.a0 + R.b0;
+      } else if (R.mode == 1) {
+        ok = read_span(R, R.ids[j], s0, e0);
+      } else {
+        const lz_request q = R.reqs[j];
+        if (q.kind == 0) {
+          ok = read_span(R, q.a, s0, e0);
+        } else if (q.kind == 1 && q.a >= 0 && q.b >= 0 && (uint64_t)q.a <= R.n && (uint64_t)q.b <= R.n - (uint64_t)q.a) {
+          s0 = (uint64_t)q.a;
+          e0 = s0 + (uint64_t)q.b;
+        } else {
+          ok = false;
+        }
+      }
+      if (!ok) {
+        latch(R.ctl, kStRange);
+        s0 = e0 = 0;
+      }
+      R.spans[2 * j] = s0;
+      R.spans[2 * j + 1] = e0;
+    }
+    const uint64_t len = e0 - s0;
+    const uint64_t cnt = e0 > s0 ? ((e0 - 1) >> R.bl) - (s0 >> R.bl) + 1 : 0;
+    uint64_t il = len, ic = cnt;
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint64_t yl = __shfl_up(il, d, 64), yc = __shfl_up(ic, d, 64);
+      if (lane >= (uint32_t)d) { il += yl; ic += yc; }
+    }
+    if (lane == 63) { wsum[0][wv] = il; wsum[1][wv] = ic; }
+    __syncthreads();
+    uint64_t bl = 0, bc = 0, tl = 0, tc = 0;
+    for (uint32_t q = 0; q < kPlanWG / 64; q++) {
+      if (q < wv) { bl += wsum[0][q]; bc += wsum[1][q]; }
+      tl += wsum[0][q];
+      tc += wsum[1][q];
+    }
+    if (j < nreq) {
+      R.offs[j] = carry_len + bl + il - len;
+      R.cnt_ptr[j] = carry_cnt + bc + ic - cnt;
+      if (R.offsets) R.offsets[j] = carry_len + bl + il - len;
+    }
+    carry_len += tl;
+    carry_cnt += tc;
+    __syncthreads();
+  }
+  if (t == 0) {
+    R.offs[nreq] = carry_len;
+    R.cnt_ptr[nreq] = carry_cnt;
+    if (R.offsets) R.offsets[nreq] = carry_len;
+    *ctl64(R.ctl, kCtlTotal) = carry_len;
+    uint64_t pairs = carry_cnt;
+    if (carry_len > R.cap) {
+      latch(R.ctl, kStCapacity);
+      pairs = 0;                 // nothing is decoded or gathered
+    }
+    *ctl64(R.ctl, kCtlPairs) = pairs;
+    s_pairs = pairs;
+  }
+  __syncthreads();
+  // covering blocks: marked with this epoch and listed once each
+  const uint64_t pairs = s_pairs;
+  auto push = [&](uint32_t b) {
+    const uint32_t old = __hip_atomic_fetch_max(R.mark + b, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old >= epoch) return;
+    const uint32_t i = atomicAdd(&s_tail, 1u);
+    if (i < R.n_blocks) R.list[i] = ((uint64_t)epoch << 32) | b;
+  };
+  for (uint64_t g = t; g < pairs; g += kPlanWG) {
+    const uint32_t j = find_req(R.cnt_ptr, nreq, g);
+    push((uint32_t)((R.spans[2 * j] >> R.bl) + (g - R.cnt_ptr[j])));
+  }
+  __syncthreads();
+  // dependency closure, one round per pass over the entries listed so far
+  uint32_t head = 0;
+  for (uint32_t round = 0; round <= R.n_blocks; round++) {
+    const uint32_t tail = min(s_tail, (uint32_t)R.n_blocks);
+    if (head >= tail) break;
+    for (uint32_t i = head + t; i < tail; i += kPlanWG) {
+      const uint32_t b = (uint32_t)R.list[i];
+      const uint64_t d0 = ld64(R.arc + R.off_dep_ptr + 8ull * b), d1 = ld64(R.arc + R.off_dep_ptr + 8ull * (b + 1));
+      for (uint64_t k = d0; k < d1; k++) push(ld32(R.arc + R.off_dep_idx + 4 * k));
+    }
+    head = tail;
+    __syncthreads();
+  }
+  const uint32_t cnt = min(s_tail, (uint32_t)R.n_blocks);
+  // levels and addresses: straight into the output for a block wholly inside
+  // an aligned single range, else a scratch slot
+  const uint64_t B = 1ull << R.bl;
+  for (uint32_t i = t; i < cnt; i += kPlanWG) {
+    const uint32_t b = (uint32_t)R.list[i];
+    atomicAdd(&lvl_cnt[block_level(R, b)], 1u);
+    const uint64_t sb = (uint64_t)b << R.bl, eb = min(sb + B, R.n);
+    uint64_t a = 0;
+    if (R.direct && sb >= R.a0 && eb <= R.a0 + R.b0 && ((sb - R.a0) & 15) == 0) {
+      a = reinterpret_cast<uint64_t>(R.out + (sb - R.a0));
+    } else {
+      const uint32_t slot = atomicAdd(&s_slots, 1u);
+      if (slot < R.max_slots) a = reinterpret_cast<uint64_t>(R.slots + (uint64_t)slot * B);
+      else latch(R.ctl, kStCapacity);
+    }
+    R.addr[b] = a;
+  }
+  __syncthreads();
+  if (t < 64) {                                 // exclusive scan of the 64 level counts
+    const uint32_t c = lvl_cnt[t];
+    uint32_t incl = c;
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(incl, d, 64);
+      if (t >= (uint32_t)d) incl += y;
+    }
+    R.rlevel_ptr[t] = incl - c;
+    R.rlevel_ptr[65 + t] = incl - c;
+    lvl_cur[t] = incl - c;
+    if (t == 63) R.rlevel_ptr[64] = incl;
+  }
+  __syncthreads();
+  for (uint32_t i = t; i < cnt; i += kPlanWG) {
+    const uint32_t b = (uint32_t)R.list[i];
+    R.rqueue[atomicAdd(&lvl_cur[block_level(R, b)], 1u)] = b;
+  }
+  if (t == 0) {
+    R.ctl[kCtlListTail] = cnt;
+    R.ctl[kCtlSlots] = s_slots;
+    if (s_tail > R.n_blocks) latch(R.ctl, kStCorrupt);
+  }
+}
+
 // One workgroup per (request, covering block) pair: copy the requested part
 // of a block that was decoded into a scratch slot.
 __global__ void k_req_gather(ReqArgs R) {
@@ -1624,15 +1805,26 @@ int lz_launch_requests(lz_handle* h, const lz_request* d_reqs, const uint32_t* d
   R.ctl = h->ws.ctl;
   const uint32_t spin = h->tune.spin_limit ? h->tune.spin_limit : (1u << 20);
   const uint32_t g_req = (uint32_t)std::min<uint64_t>(1024, (n_max + 255) / 256);
+  // small calls are planned by one workgroup (one launch instead of eight):
+  // at most 4096 covering blocks expected (a range, reads at two blocks each,
+  // batches of up to 16 requests)
+  const uint64_t Bs = 1ull << v.block_log2;
+  const bool small = R.mode == 0 ? single_len / Bs + 2 <= 4096
+                   : R.mode == 1 ? n_max * (v.max_record_len / Bs + 2) <= 4096
+                                 : n_max <= 16;
   const uint32_t g_wide = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(1024, (v.n_blocks + 255) / 256));
-  hipLaunchKernelGGL(k_req_begin, dim3(1), dim3(256), 0, s, R);
-  hipLaunchKernelGGL(k_req_spans, dim3(g_req), dim3(256), 0, s, R);
-  hipLaunchKernelGGL(k_req_scan, dim3(1), dim3(1024), 0, s, R);
-  hipLaunchKernelGGL(k_req_mark, dim3(g_wide), dim3(256), 0, s, R);
-  hipLaunchKernelGGL(k_closure, dim3(std::min<uint32_t>(64, g_wide)), dim3(256), 0, s, R, spin);
-  hipLaunchKernelGGL(k_req_levels, dim3(g_wide), dim3(256), 0, s, R);
-  hipLaunchKernelGGL(k_req_level_scan, dim3(1), dim3(64), 0, s, R);
-  hipLaunchKernelGGL(k_req_scatter, dim3(g_wide), dim3(256), 0, s, R);
+  if (small) {
+    hipLaunchKernelGGL(k_req_plan, dim3(1), dim3(kPlanWG), 0, s, R);
+  } else {
+    hipLaunchKernelGGL(k_req_begin, dim3(1), dim3(256), 0, s, R);
+    hipLaunchKernelGGL(k_req_spans, dim3(g_req), dim3(256), 0, s, R);
+    hipLaunchKernelGGL(k_req_scan, dim3(1), dim3(1024), 0, s, R);
+    hipLaunchKernelGGL(k_req_mark, dim3(g_wide), dim3(256), 0, s, R);
+    hipLaunchKernelGGL(k_closure, dim3(std::min<uint32_t>(64, g_wide)), dim3(256), 0, s, R, spin);
+    hipLaunchKernelGGL(k_req_levels, dim3(g_wide), dim3(256), 0, s, R);
+    hipLaunchKernelGGL(k_req_level_scan, dim3(1), dim3(64), 0, s, R);
+    hipLaunchKernelGGL(k_req_scatter, dim3(g_wide), dim3(256), 0, s, R);
+  }
   // decode the closure in level order (one cooperative launch, or one launch per level)
   DevArgs A = make_args(h);
   A.queue = h->ws.rqueue;
