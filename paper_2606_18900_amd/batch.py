@@ -72,8 +72,8 @@ class Batcher:
         else:
             self._launch()
 
-    def event(self) -> torch.cuda.Event:
-        e = torch.cuda.Event()
+    def event(self, timing: bool = False) -> torch.cuda.Event:
+        e = torch.cuda.Event(enable_timing=timing)
         e.record(self.stream)
         return e
 

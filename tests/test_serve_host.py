@@ -50,7 +50,7 @@ class FakeLane:
         FakeLane.log.append((len(kind), sum(len(o) for o in out)))
         self.res = out
 
-    def event(self):
+    def event(self, timing=False):
         return _Ev()
 
     def synchronize(self):
@@ -89,3 +89,44 @@ def test_serve_host_budget():
     x = _source(50_000, 4)
     with pytest.raises(ValueError):
         Server([FakeArc(x)], [None], budget=1000, lanes=1, n_max=4, window=4096, batcher=FakeLane)
+
+
+def test_serve_host_refuses_read_larger_than_window():
+    """A read whose record cannot fit one window is refused with LZ_EBUDGET
+    (it could never be served within the budget) instead of being queued
+    forever; every other request is still served exactly."""
+    from paper_2606_18900_amd._lib import LZ_EBUDGET
+    x = _source(100_000, 5)
+    starts = np.array([0, 1000, 9000, 9500, 100_000], dtype=np.int64)   # record 3 is 90,500 bytes
+    FakeLane.starts = starts
+    tr = {"t": np.array([0.0, 0.0, 0.0, 0.0]), "archive": np.zeros(4, dtype=np.int64),
+          "kind": np.zeros(4, dtype=np.int64), "a": np.array([0, 1, 2, 3]), "b": np.zeros(4, dtype=np.int64)}
+    srv = Server([FakeArc(x)], [starts], budget=64 << 20, lanes=2, n_max=4, window=10_000,
+                 keep_results=True, batcher=FakeLane)
+    res = srv.run(tr)
+    assert res["completed"] == 3 and res["refused"] == {"LZ_EBUDGET": 1}
+    assert res["refused_ids"] == {3: LZ_EBUDGET}
+    for rid in (0, 1, 2):
+        assert res["results"][rid] == x[starts[rid]:starts[rid + 1]]
+
+
+class _NeverEv:
+    def query(self):
+        return False
+
+
+class StuckLane(FakeLane):
+    def event(self, timing=False):
+        return _NeverEv()
+
+
+def test_serve_host_stall_raises():
+    """A loop that cannot make progress (a batch that never completes) raises
+    after stall_s instead of spinning forever."""
+    x = _source(50_000, 6)
+    tr = {"t": np.array([0.0]), "archive": np.zeros(1, dtype=np.int64), "kind": np.ones(1, dtype=np.int64),
+          "a": np.array([0]), "b": np.array([1000])}
+    srv = Server([FakeArc(x)], [None], budget=64 << 20, lanes=1, n_max=4, window=4096,
+                 batcher=StuckLane, stall_s=0.5)
+    with pytest.raises(RuntimeError):
+        srv.run(tr)
