@@ -31,8 +31,8 @@ HBM_PEAK_GBPS = 8000.0      # MI355X HBM3E
 # decode), each scaled by what the same counter reads for a 1 GiB device copy
 # (`bench.py --legs copy`: FETCH_SIZE x 1.99995, WRITE_SIZE x 1.0).  Reported
 # only while the decoder source is the one the counters were taken on.
-PMC_TRAFFIC = {"kernels_sha256_16": "94050fe4cb0e13cd", "bytes": 1 << 30,
-               "fetch": 597849416, "write": 1073741536}
+PMC_TRAFFIC = {"kernels_sha256_16": "4c8a1b633e2958c3", "bytes": 1 << 30,
+               "fetch": 600716425, "write": 1073741517}
 
 
 def log(msg: str) -> None:
@@ -573,6 +573,7 @@ def main() -> int:
     if args.legs == "serve":
         return serve_leg(args, arc, x, starts)
     if args.legs == "reads":        # single-read latency only (for kernel traces)
+        arc.set_tuning(sync_mode=0, wg_per_cu=3)
         print(json.dumps({"read_access_us": read_latency(arc, starts, 200, dev)}), flush=True)
         return 0
     # both launch modes: one launch per dependency level, and one persistent
