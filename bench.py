@@ -19,7 +19,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# FASTQ profile used for the archive (container format v1 parameters)
+# FASTQ profile used for the archive (container format v2 parameters)
 FASTQ_PARAMS = dict(kind=1, block_log2=14, max_level=64, min_match=16, hash_len=16,
                     hash_bits=30, chain_depth=16, window_log2=0, lit_lanes=256,
                     seq_lanes=64, prob_bits=(12, 10, 10, 10), level_penalty=32)

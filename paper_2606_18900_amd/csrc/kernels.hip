@@ -62,7 +62,7 @@ constexpr uint32_t kClkSlots = 16;                // stage clocks: 9 stages, blo
 #define CLK_NOW() 0ull
 #endif
 
-// All LDS is static (53,240 B: three workgroups per CU).
+// All LDS is static (52,832 B: three workgroups per CU).
 struct Smem {
   uint32_t lut[kLutLit];       // literal decode entries: symbol | f << 8 | (slot - c) << 20
   alignas(16) uint8_t tile[kB];// output tile; until stage 3 a copy of the payload prefix
