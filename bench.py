@@ -419,7 +419,7 @@ def serve_leg(args, arq, xq, starts) -> int:
 
 STAGES = ["payload copy", "stream headers", "short streams (CMD, MLEN, OFF)",
           "block scan, match lists", "literal decode and placement", "matches from earlier blocks",
-          "in-block match fields and ranges", "in-block match passes", "tile store"]
+          "in-block match fields", "in-block passes (next block prepared meanwhile)", "tile store"]
 
 
 def stage_clocks(arc, out) -> int:
@@ -447,6 +447,8 @@ def stage_clocks(arc, out) -> int:
     log("  wave 0, per block: %.2f in-block passes, %.2f slow in-block matches taking %.0f cycles; "
         "%.2f literal ring refills taking %.0f cycles" % (v[10] / blocks, v[11] / blocks, v[12] / blocks,
                                                         v[14] / blocks, v[13] / blocks))
+    log("  blocks whose stages 0-1 ran during the previous block's in-block stage: %.1f %%"
+        % (100.0 * v[15] / blocks))
     return 0
 
 

@@ -37,6 +37,7 @@ constexpr uint32_t kLutLit = 1u << kMaxPLit;      // 4096 packed literal entries
 constexpr uint32_t kL = 1u << 16;                 // rANS state lower bound
 constexpr uint32_t kFastLen = 64;                 // in-block matches copied by one lane
 constexpr uint32_t kClkSlots = 16;                // stage clocks: 9 stages, block count, events
+constexpr uint32_t kPrepRing = kWaves * 256 * 6;  // bytes of the two literal rings
 
 // Stage clocks (instrumented build only, -DLZ_STAGE_CLOCKS): a barrier, then
 // thread 0 adds the cycles since the previous mark to stage i.  The product
@@ -78,11 +79,21 @@ struct Smem {
   uint16_t lst[kMaxSeq];       // [0, n_ext): matches from earlier blocks (any order);
                                // [kMaxSeq - n_in, kMaxSeq): in-block matches, last first;
                                // stage 4: dependency range of in-block match a
-  uint16_t ring[kWaves][256];  // rANS words of the literal stream staged per wave
-  uint32_t ringe[kWaves][256]; // table entry of each staged word's slot
+  union {
+    struct {
+      uint16_t ring[kWaves][256];  // rANS words of the literal stream staged per wave
+      uint32_t ringe[kWaves][256]; // table entry of each staged word's slot
+    };
+    alignas(16) uint8_t prep[kPrepRing];   // between literal stages: the next block's
+                                           // payload prefix (prep_ring)
+  };
+  uint16_t fdst[64], flen[64], frng[64];   // at most 64 in-block matches: destination,
+  uint32_t fpk[64];                        // length, dependency range, source | period
+  uint32_t pst[7];             // literal record of the prepared block
+  uint32_t pok, pring, phlen;  // prepared block: records valid, copy in prep[], copy length
   uint32_t dummy[64];          // target of the masked-off lanes' byte stores
   uint32_t scan[3][kWaves];
-  uint32_t item, err, next, nin;
+  uint32_t item, err, perr, next, nin;
 #ifdef LZ_STAGE_CLOCKS
   uint64_t clk[kClkSlots], clk_last;
 #endif
@@ -486,47 +497,179 @@ struct PutPlanes {
   }
 };
 
-// Decode block b into the LDS tile and store it.  Every loop below is bounded
-// by values read from global memory (directory, stream headers).
-__device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
-  const uint32_t t = threadIdx.x, wv = uni(t >> 6), lane = lane_id();
-  const uint64_t B = 1ull << A.bl;
-  const uint64_t sb = (uint64_t)b << A.bl;
-  const uint32_t blen = (uint32_t)((sb + B <= A.n) ? B : A.n - sb);
-  const uint8_t* de = A.arc + A.off_dir + (uint64_t)b * kDirEntry;
-  const uint64_t poff = ld64(de);
-  const uint32_t plen = ld32(de + 8), ns = ld32(de + 12), nlit = ld32(de + 16);
-  const uint8_t* pay = A.arc + A.off_payload + poff;
-  CLK_START(S);
+// Where block b's payload lies and how many sequences and literals it holds.
+struct BlockDir {
+  uint64_t poff;
+  uint32_t plen, ns, nlit, blen;
+};
 
-  // ---- stage 0: the first min(plen, 16 KiB) payload bytes into the tile
-  // (free until stage 3) with one round of 16-byte loads: the stream headers
-  // and the short streams (at most about 9.3 KB with their headers for 1025
-  // sequences) are read from there; the literal stream from HBM.
-  const uint32_t hlen = min(plen, kB);
+__device__ __forceinline__ BlockDir block_dir(const DevArgs& A, uint32_t b) {
+  const uint64_t B = 1ull << A.bl, sb = (uint64_t)b << A.bl;
+  const uint8_t* de = A.arc + A.off_dir + (uint64_t)b * kDirEntry;
+  BlockDir d;
+  d.poff = ld64(de);
+  d.plen = ld32(de + 8);
+  d.ns = ld32(de + 12);
+  d.nlit = ld32(de + 16);
+  d.blen = (uint32_t)((sb + B <= A.n) ? B : A.n - sb);
+  return d;
+}
+
+// The four stream records (CMD, MLEN, OFF, LIT) parsed and checked from the
+// LDS copy hp of the block's first hlen payload bytes (every thread parses
+// the same bytes, so the result is wave-uniform).
+__device__ __forceinline__ bool parse_records(const DevArgs& A, const BlockDir& d, const uint8_t* hp,
+                                              uint32_t hlen, Stream& sc, Stream& sm, Stream& so,
+                                              Stream& sl) {
+  uint32_t off = 0;
+  bool ok = d.ns >= 1 && d.ns <= kMaxSeq && d.nlit <= d.blen && (d.poff & 15) == 0;
+  ok = ok && parse_stream(hp, hlen, d.plen, &off, 2 * d.ns, A.seq_lanes, true, sc);
+  ok = ok && parse_stream(hp, hlen, d.plen, &off, 2 * d.ns, A.seq_lanes, true, sm);
+  ok = ok && parse_stream(hp, hlen, d.plen, &off, A.w * d.ns, A.seq_lanes, true, so);
+  ok = ok && parse_stream(hp, hlen, d.plen, &off, d.nlit, A.lit_lanes, false, sl);
+  return ok;
+}
+
+// Short stream `role` of a block with ns sequences, by one wave: 0 CMD ->
+// lit[] (LL), 1 MLEN -> out[] (ML), 2 OFF -> oflo/ofhi (absolute offsets).
+__device__ bool short_stream(Smem& S, const DevArgs& A, uint32_t role, const Stream& s,
+                             const uint8_t* hp, uint32_t ns) {
+  const uint32_t lane = lane_id();
+  PutPlanes put;
+  put.ns = ns;
+  if (role < 2) {
+    put.lo = role == 0 ? reinterpret_cast<uint8_t*>(S.lit) : reinterpret_cast<uint8_t*>(S.out);
+    put.hi = put.lo;
+    put.stride = 2;
+  } else {
+    put.lo = reinterpret_cast<uint8_t*>(S.oflo);
+    put.hi = S.ofhi;
+    put.stride = 4;
+    // offsets narrower than 5 bytes: clear the planes the stream does not hold
+    for (uint32_t j = lane; j < ns; j += 64) { S.oflo[j] = 0; S.ofhi[j] = 0; }
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (s.mode == kModeRans) {
+    const uint32_t P = A.P[1 + role];
+    const uint32_t bs = P > 8 ? P - 8 : 0u;
+    return short_rans(hp + s.body, s, P, S.cum[role], S.bkt[role], bs, put);
+  }
+  if (s.mode == kModeRaw || s.mode == kModeConst) {
+    const uint8_t* src = hp + s.body;
+    for (uint32_t i = lane; i < s.n; i += 64) {
+      put.start(i);
+      put(s.mode == kModeRaw ? (uint32_t)src[i] : s.csym);
+    }
+  }
+  return true;
+}
+
+// The literal record of the prepared block, for the literal stage.
+__device__ __forceinline__ void put_lit(Smem& S, const Stream& s) {
+  S.pst[0] = s.mode; S.pst[1] = s.csym; S.pst[2] = s.K; S.pst[3] = s.n;
+  S.pst[4] = s.nw; S.pst[5] = s.blen; S.pst[6] = s.body;
+}
+
+// Stages 0 and 1 of block b ("preparing" it): the payload prefix is copied
+// into LDS, the four stream records are parsed and checked, and the CMD, MLEN
+// and OFF streams are decoded into the sequence tables.  The literal record
+// goes to S.pst, the outcome to S.pok, the place of the copy to S.pring and
+// S.phlen; a short stream that fails its checks sets S.perr.
+//
+// prep_tile: all four waves.  The first min(plen, 16 KiB) payload bytes go
+// into the tile (free until the literal stage) with one round of 16-byte
+// loads; waves 0..2 decode the short streams from there (at most about 9.3 KB
+// with their headers for 1025 sequences).  Corrupt records are latched.
+__device__ void prep_tile(Smem& S, const DevArgs& A, uint32_t b) {
+  const uint32_t t = threadIdx.x, wv = uni(t >> 6), lane = lane_id();
+  const BlockDir d = block_dir(A, b);
+  const uint8_t* pay = A.arc + A.off_payload + d.poff;
+  CLK_START(S);
+  const uint32_t hlen = min(d.plen, kB);
   {
     const uint4* src4 = reinterpret_cast<const uint4*>(pay);
     uint4* dst4 = reinterpret_cast<uint4*>(S.tile);
     for (uint32_t c = t; c < (hlen >> 4); c += kWG) dst4[c] = src4[c];
     if (t < (hlen & 15u)) S.tile[(hlen & ~15u) + t] = pay[(hlen & ~15u) + t];
   }
-  if (t == 0) { S.err = 0; S.nin = 0; S.next = 0; }
+  if (t == 0) { S.perr = 0; S.next = 0; }
   __syncthreads();
   CLK_MARK(S, 0);
-  const uint8_t* hp = S.tile;
-
-  // stream records: CMD, MLEN, OFF, LIT (every thread parses the same bytes)
   Stream sc, sm, so, sl;
-  uint32_t off = 0;
-  bool ok = ns >= 1 && ns <= kMaxSeq && nlit <= blen && (poff & 15) == 0;
-  ok = ok && parse_stream(hp, hlen, plen, &off, 2 * ns, A.seq_lanes, true, sc);
-  ok = ok && parse_stream(hp, hlen, plen, &off, 2 * ns, A.seq_lanes, true, sm);
-  ok = ok && parse_stream(hp, hlen, plen, &off, A.w * ns, A.seq_lanes, true, so);
-  ok = ok && parse_stream(hp, hlen, plen, &off, nlit, A.lit_lanes, false, sl);
-  if (!ok) {
-    if (t == 0) latch(A.ctl, kStCorrupt);
-    return;
+  const bool ok = parse_records(A, d, S.tile, hlen, sc, sm, so, sl);
+  if (t == 0) {
+    S.pok = ok ? 1u : 0u;
+    S.pring = 0;
+    S.phlen = hlen;
+    put_lit(S, sl);
+    if (!ok) latch(A.ctl, kStCorrupt);
   }
+  CLK_MARK(S, 1);
+  if (ok && wv < 3) {
+    const Stream& s = wv == 0 ? sc : (wv == 1 ? sm : so);
+    if (!short_stream(S, A, wv, s, S.tile, d.ns) && lane == 0) S.perr = 1;
+  }
+  __syncthreads();
+  CLK_MARK(S, 2);
+}
+
+// prep_ring: waves 1..3 only, while wave 0 resolves the previous block's
+// in-block matches, so no workgroup barrier may be used.  Every wave copies
+// the same first kPrepRing payload bytes into the literal rings (idle from
+// the end of the literal stage to the next one) itself, so each needs only
+// its own stores before it reads; waves 1..3 decode CMD, MLEN and OFF.  A
+// prefix too short for the short streams and the literal record's states and
+// counts (or corrupt records) leaves S.pok 0, and the block is prepared again
+// by prep_tile.  The caller guarantees that the sequence tables, S.pst and
+// the rings are not in use.
+__device__ void prep_ring(Smem& S, const DevArgs& A, uint32_t b) {
+  const uint32_t wv = uni(threadIdx.x >> 6), lane = lane_id();
+  const BlockDir d = block_dir(A, b);
+  const uint8_t* pay = A.arc + A.off_payload + d.poff;
+  const uint32_t hlen = min(d.plen, kPrepRing);
+  {
+    const uint4* src4 = reinterpret_cast<const uint4*>(pay);
+    uint4* dst4 = reinterpret_cast<uint4*>(S.prep);
+    for (uint32_t c = lane; c < (hlen >> 4); c += 64) dst4[c] = src4[c];
+    if (lane < (hlen & 15u)) S.prep[(hlen & ~15u) + lane] = pay[(hlen & ~15u) + lane];
+  }
+  __builtin_amdgcn_wave_barrier();
+  Stream sc, sm, so, sl;
+  const bool ok = parse_records(A, d, S.prep, hlen, sc, sm, so, sl);
+  bool okw = true;
+  if (ok) {
+    const uint32_t role = wv - 1;
+    const Stream& s = role == 0 ? sc : (role == 1 ? sm : so);
+    okw = short_stream(S, A, role, s, S.prep, d.ns);
+  }
+  if (!okw && lane == 0) S.perr = 1;
+  if (wv == 1 && lane == 0) {
+    S.pok = ok ? 1u : 0u;
+    S.pring = 1;
+    S.phlen = hlen;
+    put_lit(S, sl);
+    S.next = 0;
+  }
+}
+
+// Decode block b, prepared by prep_tile or prep_ring (S.pok, S.pst and the
+// sequence tables hold its stages 0 and 1), into the LDS tile and store it.
+// nb is the workgroup's next block or ~0u; the result is true when nb has
+// been prepared meanwhile, by waves 1..3 while wave 0 resolved b's in-block
+// matches.  Every loop below is bounded by values read from global memory
+// (directory, stream headers).
+__device__ bool decode_block(Smem& S, const DevArgs& A, uint32_t b, uint32_t nb) {
+  const uint32_t t = threadIdx.x, wv = uni(t >> 6), lane = lane_id();
+  const BlockDir dir = block_dir(A, b);
+  const uint64_t sb = (uint64_t)b << A.bl;
+  const uint32_t blen = dir.blen, ns = dir.ns, nlit = dir.nlit;
+  const uint8_t* pay = A.arc + A.off_payload + dir.poff;
+  if (!uni(S.pok)) return false;               // corrupt records (latched by prep_tile)
+  Stream sl;
+  sl.mode = uni(S.pst[0]); sl.csym = uni(S.pst[1]); sl.K = uni(S.pst[2]); sl.n = uni(S.pst[3]);
+  sl.nw = uni(S.pst[4]); sl.blen = uni(S.pst[5]); sl.body = uni(S.pst[6]);
+  const uint8_t* hp = uni(S.pring) ? S.prep : S.tile;
+  const uint32_t hlen = uni(S.phlen);
   // literal group of this wave (K <= 256: at most one per wave), fetched ahead
   const uint32_t Glit = sl.mode == kModeRans ? (sl.K + 63) >> 6 : 0u;
   LitPre lp;
@@ -534,43 +677,7 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
     const uint32_t co = sl.body + 4 * sl.K;     // group word counts: from the copy when inside it
     lit_prefetch(pay + sl.body, co + 4 * Glit <= hlen ? hp + co : pay + co, sl.K, wv, lp);
   }
-  CLK_MARK(S, 1);
-
-  // ---- stage 1: CMD -> lit[] (LL), MLEN -> out[] (ML), OFF -> oflo/ofhi
-  if (wv < 3) {
-    const Stream& s = wv == 0 ? sc : (wv == 1 ? sm : so);
-    PutPlanes put;
-    put.ns = ns;
-    if (wv < 2) {
-      put.lo = wv == 0 ? reinterpret_cast<uint8_t*>(S.lit) : reinterpret_cast<uint8_t*>(S.out);
-      put.hi = put.lo;
-      put.stride = 2;
-    } else {
-      put.lo = reinterpret_cast<uint8_t*>(S.oflo);
-      put.hi = S.ofhi;
-      put.stride = 4;
-    }
-    // offsets narrower than 5 bytes: clear the planes the stream does not hold
-    if (wv == 2) {
-      for (uint32_t j = lane; j < ns; j += 64) { S.oflo[j] = 0; S.ofhi[j] = 0; }
-      __builtin_amdgcn_wave_barrier();
-    }
-    bool okw = true;
-    if (s.mode == kModeRans) {
-      const uint32_t P = A.P[1 + wv];
-      const uint32_t bs = P > 8 ? P - 8 : 0u;
-      okw = short_rans(hp + s.body, s, P, S.cum[wv], S.bkt[wv], bs, put);
-    } else if (s.mode == kModeRaw || s.mode == kModeConst) {
-      const uint8_t* src = hp + s.body;
-      for (uint32_t i = lane; i < s.n; i += 64) {
-        put.start(i);
-        put(s.mode == kModeRaw ? (uint32_t)src[i] : s.csym);
-      }
-    }
-    if (!okw && lane == 0) S.err = 1;
-  }
-  __syncthreads();
-  CLK_MARK(S, 2);
+  if (t == 0) S.err = 0;
 
   // ---- stage 2: command placement.  One block scan of (LL, LL + ML,
   // in-block match) counts gives literal and output positions and the order
@@ -632,9 +739,9 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
     if (bad) S.err = 1;
   }
   __syncthreads();
-  if (S.err) {
+  if (S.err || S.perr) {
     if (t == 0) latch(A.ctl, kStCorrupt);
-    return;
+    return false;
   }
   CLK_MARK(S, 3);
 
@@ -747,9 +854,10 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
   __syncthreads();
   if (S.err) {
     if (t == 0) latch(A.ctl, kStCorrupt);
-    return;
+    return false;
   }
   CLK_MARK(S, 5);
+  if (t == 0) S.perr = 0;   // every thread has read it (stage 2): free for the next block
 
   // ---- stage 4: matches whose source touches the block itself.
   // With period d = p - OF, out[p+k] = out[OF + (k mod d)] for every k (the
@@ -758,16 +866,57 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
   // 4a: per match a (sequence order): destination, length, block-relative
   //     source and period, and the index range of earlier in-block matches
   //     whose destinations its window meets (two binary searches over the
-  //     sorted, disjoint destinations), packed into the sequence tables;
+  //     sorted, disjoint destinations);
   // 4b: wave 0 copies them in passes over 64-entry chunks (every earlier
   //     chunk complete): a pass takes every pending match whose predecessors
   //     are done.  Short matches (at most 64 bytes, no overlap with themselves,
   //     source inside the tile) are copied by their own lane from four-byte
   //     words; the others by the whole wave, one at a time.
+  // With at most 64 in-block matches (the common case) their fields go to
+  // their own small arrays and only wave 0 works on them after the first
+  // barrier; the sequence tables are then free, and waves 1..3 prepare the
+  // next block meanwhile.  With more, the fields are packed into the sequence
+  // tables and 4a uses every thread.
   const uint32_t cnt = min(S.nin, ns);
+  const bool small = cnt <= 64;
+  uint16_t* Fd = small ? S.fdst : S.lit;     // destination
+  uint16_t* Fl = small ? S.flen : S.out;     // length
+  uint32_t* Fp = small ? S.fpk : S.oflo;     // source | period << 16
+  uint16_t* Fr = small ? S.frng : S.lst;     // dependency range within the chunk
+  uint32_t md0[5], mM[5], ms[5], md[5];
+  const uint32_t per = (cnt + kWG - 1) / kWG, a0 = min(cnt, t * per), a1 = min(cnt, a0 + per);
+  // dependency ranges of this thread's matches (reads Fd, Fl of earlier ones)
+  auto ranges = [&]() {
+#pragma unroll
+    for (uint32_t u = 0; u < 5; u++) {
+      const uint32_t a = a0 + u;
+      if (a < a1) {
+        const int32_t s = (int32_t)ms[u] - 16384;
+        const uint32_t w = min(md[u], mM[u]);
+        uint32_t lo = a, hi = a;
+        if (s + (int32_t)w > 0) {
+          const uint32_t ws = s > 0 ? (uint32_t)s : 0u, we = (uint32_t)(s + (int32_t)w);
+          // lo = first earlier match whose destination ends after ws, hi =
+          // first whose destination starts at or after we (hi >= lo)
+          uint32_t l1 = 0, h1 = a, l2 = 0, h2 = a;
+          while (l1 < h1 || l2 < h2) {
+            const uint32_t m1 = (l1 + h1) >> 1, m2 = (l2 + h2) >> 1;
+            const uint32_t e1 = (uint32_t)Fd[min(m1, a - 1)] + Fl[min(m1, a - 1)];
+            const uint32_t b2 = Fd[min(m2, a - 1)];
+            if (l1 < h1) { if (e1 > ws) h1 = m1; else l1 = m1 + 1; }
+            if (l2 < h2) { if (b2 >= we) h2 = m2; else l2 = m2 + 1; }
+          }
+          lo = l1;
+          hi = l2;
+        }
+        const uint32_t c0 = a & ~63u;
+        const uint32_t plo = max(lo, c0) - c0, phi = max(hi, c0) - c0;   // both <= 63
+        Fr[a] = (uint16_t)(plo | (phi << 8));
+        Fp[a] = ms[u] | (md[u] << 16);
+      }
+    }
+  };
   if (cnt) {
-    uint32_t md0[5], mM[5], ms[5], md[5];
-    const uint32_t per = (cnt + kWG - 1) / kWG, a0 = min(cnt, t * per), a1 = min(cnt, a0 + per);
 #pragma unroll
     for (uint32_t u = 0; u < 5; u++) {
       const uint32_t a = a0 + u;
@@ -784,53 +933,35 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
       ms[u] = (uint32_t)((int64_t)of - (int64_t)sb + 16384) & 0xFFFFu;
       md[u] = dabs > of ? (uint32_t)min<uint64_t>(dabs - of, 32767) : 1u;
     }
-    __syncthreads();
+    if (!small) __syncthreads();             // Fd, Fl are the tables just read
 #pragma unroll
     for (uint32_t u = 0; u < 5; u++) {
       const uint32_t a = a0 + u;
       if (a < a1) {
-        S.lit[a] = (uint16_t)md0[u];
-        S.out[a] = (uint16_t)mM[u];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (uint32_t u = 0; u < 5; u++) {
-      const uint32_t a = a0 + u;
-      if (a < a1) {
-        const int32_t s = (int32_t)ms[u] - 16384;
-        const uint32_t w = min(md[u], mM[u]);
-        uint32_t lo = a, hi = a;
-        if (s + (int32_t)w > 0) {
-          const uint32_t ws = s > 0 ? (uint32_t)s : 0u, we = (uint32_t)(s + (int32_t)w);
-          // lo = first earlier match whose destination ends after ws, hi =
-          // first whose destination starts at or after we (hi >= lo)
-          uint32_t l1 = 0, h1 = a, l2 = 0, h2 = a;
-          while (l1 < h1 || l2 < h2) {
-            const uint32_t m1 = (l1 + h1) >> 1, m2 = (l2 + h2) >> 1;
-            const uint32_t e1 = (uint32_t)S.lit[min(m1, a - 1)] + S.out[min(m1, a - 1)];
-            const uint32_t b2 = S.lit[min(m2, a - 1)];
-            if (l1 < h1) { if (e1 > ws) h1 = m1; else l1 = m1 + 1; }
-            if (l2 < h2) { if (b2 >= we) h2 = m2; else l2 = m2 + 1; }
-          }
-          lo = l1;
-          hi = l2;
-        }
-        const uint32_t c0 = a & ~63u;
-        const uint32_t plo = max(lo, c0) - c0, phi = max(hi, c0) - c0;   // both <= 63
-        S.lst[a] = (uint16_t)(plo | (phi << 8));
-        S.oflo[a] = ms[u] | (md[u] << 16);
+        Fd[a] = (uint16_t)md0[u];
+        Fl[a] = (uint16_t)mM[u];
       }
     }
   }
-  __syncthreads();
+  __syncthreads();                           // sequence tables read; Fd, Fl written
+  if (cnt && !small) {
+    ranges();
+    __syncthreads();
+  }
   CLK_MARK(S, 6);
+  // No workgroup barrier from here to the end of the passes: wave 0 and
+  // waves 1..3 run different code.
+  const bool ov = small && nb != ~0u;
   if (wv == 0 && cnt) {
+    if (small) {
+      ranges();                              // this wave's own Fd, Fl stores precede
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
     bool bad = false;
     // whole-wave copy of in-block match a (any length, period and source)
     auto copy_match = [&](uint32_t a) {
-      const uint32_t pk = S.oflo[a];
-      const uint32_t d0 = S.lit[a], M = S.out[a];
+      const uint32_t pk = Fp[a];
+      const uint32_t d0 = Fd[a], M = Fl[a];
       const int32_t s = (int32_t)(pk & 0xFFFFu) - 16384;
       const uint32_t d = (pk >> 16) & 0x7FFFu;
       // (k mod d) kept incrementally (a division only for d < 64)
@@ -854,11 +985,11 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
       const uint32_t a = c0 + lane;
       const bool have = a < cnt;
       const uint32_t aa = have ? a : c0;
-      const uint32_t rng = S.lst[aa];
+      const uint32_t rng = Fr[aa];
       const uint32_t plo = rng & 63u, phi = (rng >> 8) & 63u;
       const uint64_t needm = have && phi > plo ? (1ull << phi) - (1ull << plo) : 0ull;
-      const uint32_t pk = S.oflo[aa];
-      const uint32_t dst = S.lit[aa], len = S.out[aa];
+      const uint32_t pk = Fp[aa];
+      const uint32_t dst = Fd[aa], len = Fl[aa];
       const int32_t s = (int32_t)(pk & 0xFFFFu) - 16384;
       const uint32_t d = (pk >> 16) & 0x7FFFu;
       const bool fast = d >= len && len <= kFastLen && s >= 0;
@@ -910,13 +1041,17 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
       if (__ballot(pending)) bad = true;      // unreachable for a valid block
     }
     if (bad) S.err = 1;
+  } else if (wv != 0 && ov) {
+    prep_ring(S, A, nb);
   }
   __syncthreads();
+  const bool prepared = ov && uni(S.pok) != 0;
+  CLK_ADD(S, 15, prepared ? 1 : 0);
+  CLK_MARK(S, 7);
   if (S.err) {
     if (t == 0) latch(A.ctl, kStCorrupt);
-    return;
+    return false;
   }
-  CLK_MARK(S, 7);
 
   // ---- stage 5: tile -> HBM with 16-byte stores
   uint8_t* dst = A.addr ? reinterpret_cast<uint8_t*>(A.addr[b]) : A.out + sb;
@@ -931,7 +1066,9 @@ __device__ void decode_block(Smem& S, const DevArgs& A, uint32_t b) {
 #ifdef LZ_STAGE_CLOCKS
   if (t == 0) S.clk[9] += 1;
 #endif
+  return prepared;
 }
+
 
 // Once per workgroup: literal LUT image into LDS, small-stream cumulative tables.
 __device__ void load_tables(Smem& S, const DevArgs& A) {
@@ -1018,6 +1155,7 @@ __global__ void __launch_bounds__(kWG, 3) k_decode(DevArgs A) {   // 3 waves per
   if (t < kClkSlots) S.clk[t] = 0;
 #endif
   bool tables = false;        // tables are loaded before the workgroup's first block
+  bool prepared = false;      // the next block's stages 0 and 1 are done
   for (;;) {
     if (A.persistent) {
       while (it >= qe && L < kMaxLevels) {     // this workgroup's next block, in a later level
@@ -1036,9 +1174,12 @@ __global__ void __launch_bounds__(kWG, 3) k_decode(DevArgs A) {   // 3 waves per
       __syncthreads();
       tables = true;
     }
-    decode_block(S, A, A.queue[it]);
+    const uint32_t nit = it + gridDim.x;
+    const uint32_t b = A.queue[it], nb = nit < qe ? A.queue[nit] : ~0u;
+    if (!prepared) prep_tile(S, A, b);
+    prepared = decode_block(S, A, b, nb);
     __syncthreads();
-    it += gridDim.x;
+    it = nit;
   }
 #ifdef LZ_STAGE_CLOCKS
   __syncthreads();
