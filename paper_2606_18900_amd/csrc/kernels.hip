@@ -90,7 +90,9 @@ struct Smem {
   uint16_t fdst[64], flen[64], frng[64];   // at most 64 in-block matches: destination,
   uint32_t fpk[64];                        // length, dependency range, source | period
   uint32_t pst[7];             // literal record of the prepared block
-  uint32_t pok, pring, phlen;  // prepared block: records valid, copy in prep[], copy length
+  uint32_t pdir[4];            // its payload offset (low, high word), sequences, literals
+  uint32_t plw[kWaves], pln[kWaves];   // its literal groups' first words and word counts
+  uint32_t pok;                // prepared block: records valid
   uint32_t dummy[64];          // target of the masked-off lanes' byte stores
   uint32_t scan[3][kWaves];
   uint32_t item, err, perr, next, nin;
@@ -268,17 +270,14 @@ __device__ __forceinline__ const uint16_t* lit_words(const uint8_t* body, uint32
                : reinterpret_cast<const uint16_t*>(body);
 }
 
-// body: the record body in HBM; cnt: its group word counts (LDS copy or HBM)
-__device__ __forceinline__ void lit_prefetch(const uint8_t* body, const uint8_t* cnt, uint32_t K,
-                                             uint32_t g, LitPre& L) {
-  const uint32_t lane = lane_id(), G = (K + 63) >> 6, k = (g << 6) + lane;
-  L.woff = 0;
-  L.nwg = 0;
-  for (uint32_t q = 0; q < G; q++) {
-    const uint32_t c = uni(ld32(cnt + 4 * q));
-    if (q < g) L.woff += c;
-    if (q == g) L.nwg = c;
-  }
+// body: the record body in HBM; woff, nwg: the group's first word and word
+// count (prefix sums of the group word counts, done when the block was
+// prepared)
+__device__ __forceinline__ void lit_prefetch(const uint8_t* body, uint32_t K, uint32_t g,
+                                             uint32_t woff, uint32_t nwg, LitPre& L) {
+  const uint32_t lane = lane_id(), k = (g << 6) + lane;
+  L.woff = woff;
+  L.nwg = nwg;
   const uint16_t* W = lit_words(body, K, L);
   const uint32_t lastw = L.nwg ? L.nwg - 1 : 0;
 #pragma unroll
@@ -564,17 +563,31 @@ __device__ bool short_stream(Smem& S, const DevArgs& A, uint32_t role, const Str
   return true;
 }
 
-// The literal record of the prepared block, for the literal stage.
-__device__ __forceinline__ void put_lit(Smem& S, const Stream& s) {
+// What the later stages need of the prepared block (one thread): its
+// directory fields, the literal record and the literal groups' word ranges
+// (the group word counts lie in the copy hp: parse_stream checks that).
+__device__ __forceinline__ void put_prep(Smem& S, const BlockDir& d, const Stream& s, const uint8_t* hp,
+                                         bool ok) {
+  S.pdir[0] = (uint32_t)d.poff; S.pdir[1] = (uint32_t)(d.poff >> 32); S.pdir[2] = d.ns; S.pdir[3] = d.nlit;
   S.pst[0] = s.mode; S.pst[1] = s.csym; S.pst[2] = s.K; S.pst[3] = s.n;
   S.pst[4] = s.nw; S.pst[5] = s.blen; S.pst[6] = s.body;
+  const uint32_t G = ok && s.mode == kModeRans ? (s.K + 63) >> 6 : 0u;
+  const uint32_t* cnt = reinterpret_cast<const uint32_t*>(hp + s.body + 4 * s.K);
+  uint32_t w = 0;
+  for (uint32_t g = 0; g < kWaves; g++) {
+    const uint32_t c = g < G ? cnt[g] : 0u;
+    S.plw[g] = w;
+    S.pln[g] = c;
+    w += c;
+  }
 }
 
 // Stages 0 and 1 of block b ("preparing" it): the payload prefix is copied
 // into LDS, the four stream records are parsed and checked, and the CMD, MLEN
 // and OFF streams are decoded into the sequence tables.  The literal record
-// goes to S.pst, the outcome to S.pok, the place of the copy to S.pring and
-// S.phlen; a short stream that fails its checks sets S.perr.
+// goes to S.pst with the directory fields and literal group word ranges
+// (put_prep), the outcome to S.pok; a short stream that fails its checks sets
+// S.perr.
 //
 // prep_tile: all four waves.  The first min(plen, 16 KiB) payload bytes go
 // into the tile (free until the literal stage) with one round of 16-byte
@@ -599,9 +612,7 @@ __device__ void prep_tile(Smem& S, const DevArgs& A, uint32_t b) {
   const bool ok = parse_records(A, d, S.tile, hlen, sc, sm, so, sl);
   if (t == 0) {
     S.pok = ok ? 1u : 0u;
-    S.pring = 0;
-    S.phlen = hlen;
-    put_lit(S, sl);
+    put_prep(S, d, sl, S.tile, ok);
     if (!ok) latch(A.ctl, kStCorrupt);
   }
   CLK_MARK(S, 1);
@@ -645,9 +656,7 @@ __device__ void prep_ring(Smem& S, const DevArgs& A, uint32_t b) {
   if (!okw && lane == 0) S.perr = 1;
   if (wv == 1 && lane == 0) {
     S.pok = ok ? 1u : 0u;
-    S.pring = 1;
-    S.phlen = hlen;
-    put_lit(S, sl);
+    put_prep(S, d, sl, S.prep, ok);
     S.next = 0;
   }
 }
@@ -660,23 +669,19 @@ __device__ void prep_ring(Smem& S, const DevArgs& A, uint32_t b) {
 // (directory, stream headers).
 __device__ bool decode_block(Smem& S, const DevArgs& A, uint32_t b, uint32_t nb) {
   const uint32_t t = threadIdx.x, wv = uni(t >> 6), lane = lane_id();
-  const BlockDir dir = block_dir(A, b);
-  const uint64_t sb = (uint64_t)b << A.bl;
-  const uint32_t blen = dir.blen, ns = dir.ns, nlit = dir.nlit;
-  const uint8_t* pay = A.arc + A.off_payload + dir.poff;
+  const uint64_t B = 1ull << A.bl, sb = (uint64_t)b << A.bl;
+  const uint32_t blen = (uint32_t)((sb + B <= A.n) ? B : A.n - sb);
   if (!uni(S.pok)) return false;               // corrupt records (latched by prep_tile)
+  const uint64_t poff = (uint64_t)uni(S.pdir[0]) | ((uint64_t)uni(S.pdir[1]) << 32);
+  const uint32_t ns = uni(S.pdir[2]), nlit = uni(S.pdir[3]);
+  const uint8_t* pay = A.arc + A.off_payload + poff;
   Stream sl;
   sl.mode = uni(S.pst[0]); sl.csym = uni(S.pst[1]); sl.K = uni(S.pst[2]); sl.n = uni(S.pst[3]);
   sl.nw = uni(S.pst[4]); sl.blen = uni(S.pst[5]); sl.body = uni(S.pst[6]);
-  const uint8_t* hp = uni(S.pring) ? S.prep : S.tile;
-  const uint32_t hlen = uni(S.phlen);
   // literal group of this wave (K <= 256: at most one per wave), fetched ahead
   const uint32_t Glit = sl.mode == kModeRans ? (sl.K + 63) >> 6 : 0u;
   LitPre lp;
-  if (wv < Glit) {
-    const uint32_t co = sl.body + 4 * sl.K;     // group word counts: from the copy when inside it
-    lit_prefetch(pay + sl.body, co + 4 * Glit <= hlen ? hp + co : pay + co, sl.K, wv, lp);
-  }
+  if (wv < Glit) lit_prefetch(pay + sl.body, sl.K, wv, uni(S.plw[wv]), uni(S.pln[wv]), lp);
   if (t == 0) S.err = 0;
 
   // ---- stage 2: command placement.  One block scan of (LL, LL + ML,
