@@ -444,9 +444,9 @@ def stage_clocks(arc, out) -> int:
         log("  %-36s %8.0f" % (name, v[i] / blocks))
         tot += v[i]
     log("  %-36s %8.0f" % ("total", tot / blocks))
-    log("  wave 0, per block: %.2f in-block passes, %.2f slow in-block matches taking %.0f cycles; "
-        "%.2f literal ring refills taking %.0f cycles" % (v[10] / blocks, v[11] / blocks, v[12] / blocks,
-                                                        v[14] / blocks, v[13] / blocks))
+    log("  wave 0, per block: %.2f in-block passes, %.2f slow in-block matches taking %.0f cycles, "
+        "in-block stage %.0f cycles; wave 1: next block's preparation %.0f cycles"
+        % (v[10] / blocks, v[11] / blocks, v[12] / blocks, v[13] / blocks, v[14] / blocks))
     log("  blocks whose stages 0-1 ran during the previous block's in-block stage: %.1f %%"
         % (100.0 * v[15] / blocks))
     return 0

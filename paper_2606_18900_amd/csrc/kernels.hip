@@ -2,9 +2,9 @@
 //
 // One workgroup of 256 threads (4 waves) decodes one 16 KiB block at a time
 // into an LDS tile:
-//   0. one round of 16-byte loads copies the block's payload prefix into the
-//      tile; the four stream headers are parsed from that copy;
-//   1. waves 0..2 decode the command (CMD), match-length (MLEN) and offset
+//   0. the block's payload prefix is copied into LDS and the four stream
+//      headers are parsed from that copy;
+//   1. three waves decode the command (CMD), match-length (MLEN) and offset
 //      (OFF) streams, one each, reading their rANS words from the LDS copy;
 //   2. one block-wide scan turns literal-run and match lengths into literal
 //      and output positions (command placement), counts the matches whose
@@ -14,13 +14,16 @@
 //      literal written straight to its output position in the tile; then the
 //      matches from earlier blocks are copied from HBM;
 //   4. the matches whose source touches the block are resolved in dependency
-//      passes: a match is copied once every earlier match that writes into its
-//      source window is done; byte-sequential overlap is unrolled by period;
+//      passes by wave 0: a match is copied once every earlier match that
+//      writes into its source window is done; byte-sequential overlap is
+//      unrolled by period.  Meanwhile waves 1..3 do stages 0 and 1 of the
+//      workgroup's next block (its payload prefix goes into the literal
+//      rings, idle until the next literal stage);
 //   5. the tile is written to HBM with 16-byte stores.
 // Blocks are taken in dependency-level order ("wavefront" order, paper:
-// Background section), either one launch per level or one persistent launch
-// whose workgroups take tickets and wait on the flags of a block's
-// dependencies.  No MFMA: nothing here is a contraction.
+// Background section): either one launch per level, or one cooperative
+// launch whose workgroups walk the levels with a grid barrier between them.
+// No MFMA: nothing here is a contraction.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -53,13 +56,16 @@ constexpr uint32_t kPrepRing = kWaves * 256 * 6;  // bytes of the two literal ri
       (S).clk_last = c_;                                        \
     }                                                           \
   } while (0)
-// event counters of lane 0 of wave 0 (slots 10..15): CLK_ADD(S, i, v)
+// event counters (slots 10..15): CLK_ADD(S, i, v) by lane 0 of wave 0
 #define CLK_ADD(S, i, v) do { if (threadIdx.x == 0) (S).clk[i] += (v); } while (0)
+// the same for lane 0 of wave 1
+#define CLK_ADD1(S, i, v) do { if (threadIdx.x == 64) (S).clk[i] += (v); } while (0)
 #define CLK_NOW() __builtin_readcyclecounter()
 #else
 #define CLK_START(S) do { } while (0)
 #define CLK_MARK(S, i) do { } while (0)
 #define CLK_ADD(S, i, v) do { } while (0)
+#define CLK_ADD1(S, i, v) do { } while (0)
 #define CLK_NOW() 0ull
 #endif
 
@@ -367,15 +373,12 @@ __device__ bool lit_group(const uint8_t* body, uint32_t K, uint32_t n, uint32_t 
       pos += (uint32_t)__popcll(bal);
       if ((pos >> 7) != s0) {            // entered slice s0+1: stage s0+2, fetch s0+kPreSlices
         __builtin_amdgcn_wave_barrier(); // after every lane's read of slice s0
-        const uint64_t c0_ = CLK_NOW();
         const uint32_t ea = S.lut[rq[0] & mask], eb = S.lut[rq[1] & mask];
         const uint32_t d = ((s0 & 1) << 7) + lane;
         ring[d] = (uint16_t)rq[0];
         ring[d + 64] = (uint16_t)rq[1];
         ringe[d] = ea;
         ringe[d + 64] = eb;
-        CLK_ADD(S, 13, CLK_NOW() - c0_);
-        CLK_ADD(S, 14, 1);
 #pragma unroll
         for (uint32_t q = 0; q + 2 < 2 * kPreSlices - 4; q++) rq[q] = rq[q + 2];
         const uint32_t b3 = (s0 + kPreSlices) << 7;
@@ -957,6 +960,7 @@ __device__ bool decode_block(Smem& S, const DevArgs& A, uint32_t b, uint32_t nb)
   // No workgroup barrier from here to the end of the passes: wave 0 and
   // waves 1..3 run different code.
   const bool ov = small && nb != ~0u;
+  const uint64_t c4_ = CLK_NOW();
   if (wv == 0 && cnt) {
     if (small) {
       ranges();                              // this wave's own Fd, Fl stores precede
@@ -1046,8 +1050,10 @@ __device__ bool decode_block(Smem& S, const DevArgs& A, uint32_t b, uint32_t nb)
       if (__ballot(pending)) bad = true;      // unreachable for a valid block
     }
     if (bad) S.err = 1;
+    CLK_ADD(S, 13, CLK_NOW() - c4_);
   } else if (wv != 0 && ov) {
     prep_ring(S, A, nb);
+    CLK_ADD1(S, 14, CLK_NOW() - c4_);
   }
   __syncthreads();
   const bool prepared = ov && uni(S.pok) != 0;
