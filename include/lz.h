@@ -252,6 +252,87 @@ int lz_sync_status(lz_handle* h, hipStream_t s);
 
 const char* lz_last_error(void);
 
+/* ---- stream-separated FASTQ (Discussion, "Where ACEAPEX Stands on Ratio":
+ * read ids, sequences and quality strings stored apart gain ratio with the
+ * same codec) ------------------------------------------------------------
+ *
+ * A split container holds a 4-line FASTQ file as four kind-0 archives of its
+ * line streams -- H (id lines), S (sequence lines), P ('+' lines), Q (quality
+ * lines), each line with its newline -- plus a read index of two u64 tables:
+ * hstart[i], sstart[i] = offsets of record i's id and sequence lines in H
+ * and S (n_reads + 1 entries each).  Record i's P and Q lines start at 2 i
+ * and sstart[i]; its first file byte is hstart[i] + 2 sstart[i] + 2 i.
+ * Layout (little-endian): "LZSF", u16 version 2, u16 flags 3, u64 N, u64
+ * n_reads, u64 offsets of hstart[] and sstart[], u64 archive offsets[4]
+ * (multiples of 256) and lengths[4], u64 FNV-1a-64 of the source, u32
+ * longest record, u32 0, u64 FNV-1a-64 of bytes 0..119; then the tables and
+ * the archives, gaps zero. */
+typedef struct lz_split lz_split;
+
+typedef struct lz_split_info {
+  uint64_t n;                /* file bytes N                                   */
+  uint64_t n_reads;          /* records                                        */
+  uint64_t container_len;    /* total container bytes                          */
+  uint64_t source_fnv;       /* FNV-1a-64 of the whole file                    */
+  uint64_t workspace_bytes;  /* device workspace lz_split_open needs (the four
+                                decoded streams, then four lz_open workspaces) */
+  uint64_t stream_len[4];    /* decoded bytes of H, S, P, Q                    */
+  uint64_t archive_len[4];   /* their archive bytes                            */
+  uint32_t max_record_len;   /* longest record (file bytes)                    */
+  uint32_t reserved;
+} lz_split_info;
+
+/* Host: write the split container of a FASTQ text (records of 4 lines, each
+ * ending in '\n').  Every stream is encoded by lz_encode with *p and kind 0.
+ * EINVAL for text that is not whole records, an id line without '@', a
+ * third line other than a bare '+', or a quality line whose length differs
+ * from its sequence line's.  *out is malloc'd (free with lz_free). */
+int lz_encode_split(const uint8_t* src, uint64_t n, const lz_params* p, uint8_t** out,
+                    uint64_t* out_len);
+
+/* Device: read and check the container's headers from d_container (device,
+ * len bytes; synchronises s) and describe it. */
+int lz_split_info_get(const uint8_t* d_container, uint64_t len, hipStream_t s, lz_split_info* out);
+
+/* Bind a device-resident container (256-byte aligned) and a caller workspace
+ * of lz_split_info.workspace_bytes (256-byte aligned): the record tables are
+ * copied to the host and checked against the streams, each stream archive is
+ * opened with lz_open.  Synchronises s. */
+int lz_split_open(const uint8_t* d_container, uint64_t len, void* d_ws, uint64_t ws_len, hipStream_t s,
+                  lz_split** out);
+int lz_split_close(lz_split* sp);
+
+/* The lz_handle of stream k (0 H, 1 S, 2 P, 3 Q), owned by sp: for tuning
+ * and statistics. */
+int lz_split_stream(lz_split* sp, uint32_t k, lz_handle** out);
+
+/* d_out[0..N) = the FASTQ file: the four streams are decoded into the
+ * workspace (lz_decode_all each), then the records are reassembled in file
+ * order on the device. */
+int lz_split_decode_all(lz_split* sp, uint8_t* d_out, uint64_t cap, hipStream_t s);
+
+/* Scratch (bytes, 256-byte aligned buffer) of lz_split_decode_range (n = 1)
+ * and of lz_split_read_lookup for n ids. */
+int lz_split_scratch_bytes(const lz_split* sp, uint64_t n, uint64_t* bytes);
+
+/* d_out[0..len) = file bytes [offset, offset + len): the records covering the
+ * range are found in the host copy of the read index, their lines decoded
+ * from each stream with lz_decode_range (dependency closure included) and
+ * reassembled.  ERANGE if the range leaves the file. */
+int lz_split_decode_range(lz_split* sp, uint64_t offset, uint64_t len, uint8_t* d_out, void* d_scratch,
+                          uint64_t scratch_len, hipStream_t s);
+
+/* Records d_ids[0..n) (device int64): every stream answers a batch of range
+ * requests (lz_decode_batch) for the ids' lines, then record k is assembled
+ * at d_out[d_offsets[k] .. d_offsets[k+1]) (d_offsets: device, n + 1 u64).
+ * cap >= n * max_record_len.  An id outside [0, n_reads) is latched as
+ * ERANGE (lz_split_sync_status) and yields an empty record. */
+int lz_split_read_lookup(lz_split* sp, const int64_t* d_ids, uint64_t n, uint8_t* d_out, uint64_t cap,
+                         uint64_t* d_offsets, void* d_scratch, uint64_t scratch_len, hipStream_t s);
+
+/* lz_sync_status of the four streams: the first failure, all cleared. */
+int lz_split_sync_status(lz_split* sp, hipStream_t s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,10 @@ NAMES = {0: "LZ_OK", -1: "LZ_EINVAL", -2: "LZ_EFORMAT", -3: "LZ_ECAPACITY", -4: 
 # every symbol include/lz.h declares
 EXPORTS = ["lz_params_default", "lz_encode", "lz_free", "lz_info_get", "lz_open", "lz_close",
            "lz_get_info", "lz_set_tuning", "lz_get_tuning", "lz_decode_all", "lz_decode_range",
-           "lz_read_lookup", "lz_read_lookup_noalloc", "lz_fasta_index", "lz_decode_region", "lz_decode_batch", "lz_verify", "lz_verify_range", "lz_last_stats", "lz_sync_status", "lz_last_error"]
+           "lz_read_lookup", "lz_read_lookup_noalloc", "lz_fasta_index", "lz_decode_region", "lz_decode_batch", "lz_verify", "lz_verify_range", "lz_last_stats", "lz_sync_status", "lz_last_error",
+           "lz_encode_split", "lz_split_info_get", "lz_split_open", "lz_split_close", "lz_split_stream",
+           "lz_split_decode_all", "lz_split_scratch_bytes", "lz_split_decode_range",
+           "lz_split_read_lookup", "lz_split_sync_status"]
 
 
 class LzError(RuntimeError):
@@ -62,6 +65,13 @@ class FastaSeq(C.Structure):
                 ("line_bases", C.c_uint32), ("line_bytes", C.c_uint32)]
 
 
+class SplitInfo(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("n_reads", C.c_uint64), ("container_len", C.c_uint64),
+                ("source_fnv", C.c_uint64), ("workspace_bytes", C.c_uint64),
+                ("stream_len", C.c_uint64 * 4), ("archive_len", C.c_uint64 * 4),
+                ("max_record_len", C.c_uint32), ("reserved", C.c_uint32)]
+
+
 class Tuning(C.Structure):
     _fields_ = [("sync_mode", C.c_uint32), ("wg_per_cu", C.c_uint32), ("spin_limit", C.c_uint32)]
 
@@ -98,6 +108,16 @@ def lib():
         L.lz_sync_status.argtypes = [vp, vp]
         L.lz_free.argtypes = [vp]
         L.lz_params_default.argtypes = [vp]
+        L.lz_encode_split.argtypes = [vp, u64, vp, vp, vp]
+        L.lz_split_info_get.argtypes = [vp, u64, vp, vp]
+        L.lz_split_open.argtypes = [vp, u64, vp, u64, vp, vp]
+        L.lz_split_close.argtypes = [vp]
+        L.lz_split_stream.argtypes = [vp, u32, vp]
+        L.lz_split_decode_all.argtypes = [vp, vp, u64, vp]
+        L.lz_split_scratch_bytes.argtypes = [vp, u64, vp]
+        L.lz_split_decode_range.argtypes = [vp, u64, u64, vp, vp, u64, vp]
+        L.lz_split_read_lookup.argtypes = [vp, vp, u64, vp, u64, vp, vp, u64, vp]
+        L.lz_split_sync_status.argtypes = [vp, vp]
         _lib = L
     return _lib
 

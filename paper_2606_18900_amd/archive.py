@@ -259,3 +259,118 @@ class Archive:
 
     def sync_status(self, stream=None) -> None:
         check(lib().lz_sync_status(self.h, _stream(stream)))
+
+
+def encode_split(data, **params) -> bytes:
+    """Stream-separated FASTQ container of host bytes (lz_encode_split): the
+    id, sequence, '+' and quality lines as four archives of this codec plus a
+    read index.  Keyword arguments override lz_params fields (kind is 0)."""
+    if isinstance(data, np.ndarray):
+        a = np.ascontiguousarray(data, dtype=np.uint8)
+    else:
+        a = np.frombuffer(memoryview(data), dtype=np.uint8)
+    p = _lib.default_params(**params)
+    out = C.c_void_p()
+    n = C.c_uint64()
+    check(lib().lz_encode_split(C.c_void_p(a.ctypes.data if a.size else 0), a.size, C.byref(p),
+                                C.byref(out), C.byref(n)))
+    try:
+        return bytes(memoryview((C.c_char * n.value).from_address(out.value)))
+    finally:
+        lib().lz_free(out)
+
+
+class SplitArchive:
+    """A stream-separated FASTQ container resident in HBM (lz_split_open):
+    whole-file decode, byte ranges and read lookups of the original file."""
+
+    def __init__(self, container, device: str | torch.device = "cuda:0", stream=None):
+        self.device = torch.device(device)
+        if isinstance(container, torch.Tensor):
+            assert container.dtype == torch.uint8 and container.is_cuda and container.is_contiguous()
+            self.d_archive = container
+        else:
+            host = torch.from_numpy(np.frombuffer(memoryview(container), dtype=np.uint8).copy())
+            self.d_archive = torch.empty(host.numel(), dtype=torch.uint8, device=self.device)
+            self.d_archive.copy_(host)
+        i = _lib.SplitInfo()
+        check(lib().lz_split_info_get(_ptr(self.d_archive), self.d_archive.numel(), _stream(stream),
+                                      C.byref(i)))
+        self.info = i
+        self.ws = torch.empty(max(i.workspace_bytes, 256), dtype=torch.uint8, device=self.device)
+        self.h = C.c_void_p()
+        check(lib().lz_split_open(_ptr(self.d_archive), self.d_archive.numel(), _ptr(self.ws),
+                                  self.ws.numel(), _stream(stream), C.byref(self.h)))
+
+    @property
+    def n(self) -> int:
+        return int(self.info.n)
+
+    @property
+    def n_reads(self) -> int:
+        return int(self.info.n_reads)
+
+    def close(self):
+        if self.h:
+            lib().lz_split_close(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stream_handle(self, k: int) -> C.c_void_p:
+        h = C.c_void_p()
+        check(lib().lz_split_stream(self.h, k, C.byref(h)))
+        return h
+
+    def set_tuning(self, sync_mode: int | None = None, wg_per_cu: int | None = None):
+        for k in range(4):
+            h = self.stream_handle(k)
+            t = _lib.Tuning()
+            check(lib().lz_get_tuning(h, C.byref(t)))
+            if sync_mode is not None:
+                t.sync_mode = sync_mode
+            if wg_per_cu is not None:
+                t.wg_per_cu = wg_per_cu
+            check(lib().lz_set_tuning(h, C.byref(t)))
+
+    def scratch_bytes(self, n_requests: int) -> int:
+        b = C.c_uint64()
+        check(lib().lz_split_scratch_bytes(self.h, max(1, n_requests), C.byref(b)))
+        return int(b.value)
+
+    def decode_all(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(max(self.n, 1), dtype=torch.uint8, device=self.device)
+        check(lib().lz_split_decode_all(self.h, _ptr(out), out.numel(), _stream(stream)))
+        return out[: self.n]
+
+    def decode_range(self, offset: int, length: int, out: torch.Tensor | None = None,
+                     scratch: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(max(length, 1), dtype=torch.uint8, device=self.device)
+        if scratch is None:
+            scratch = torch.empty(self.scratch_bytes(1), dtype=torch.uint8, device=self.device)
+        check(lib().lz_split_decode_range(self.h, offset, length, _ptr(out), _ptr(scratch),
+                                          scratch.numel(), _stream(stream)))
+        return out[:length]
+
+    def read_lookup(self, ids, out: torch.Tensor | None = None, offsets: torch.Tensor | None = None,
+                    scratch: torch.Tensor | None = None, stream=None):
+        ids = torch.as_tensor(ids, dtype=torch.int64, device=self.device).contiguous()
+        n = ids.numel()
+        if out is None:
+            out = torch.empty(max(1, n * int(self.info.max_record_len)), dtype=torch.uint8, device=self.device)
+        if offsets is None:
+            offsets = torch.empty(n + 1, dtype=torch.int64, device=self.device)
+        if scratch is None:
+            scratch = torch.empty(self.scratch_bytes(n), dtype=torch.uint8, device=self.device)
+        check(lib().lz_split_read_lookup(self.h, _ptr(ids), n, _ptr(out), out.numel(), _ptr(offsets),
+                                         _ptr(scratch), scratch.numel(), _stream(stream)))
+        return out, offsets
+
+    def sync_status(self, stream=None) -> None:
+        check(lib().lz_split_sync_status(self.h, _stream(stream)))

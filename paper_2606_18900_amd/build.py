@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 INC = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "liblz.so")
 LIB_CLK = os.path.join(HERE, "liblz_clk.so")   # instrumented variant (stage clocks)
-SOURCES = ["kernels.hip", "noalloc.hip", "runtime.cpp", "encode.cpp"]
+SOURCES = ["kernels.hip", "noalloc.hip", "split.hip", "runtime.cpp", "encode.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

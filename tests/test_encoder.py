@@ -101,3 +101,29 @@ def test_segmented_parse_rejects_bad_segment_size(have_lib):
         lz.encode(b"x" * 1000, block_log2=14, segment_log2=13)   # smaller than a block
     with pytest.raises(Exception):
         lz.encode(b"x" * 1000, segment_log2=25)
+
+
+SPLIT_P = dict(block_log2=10, max_level=8, min_match=16, hash_len=16, hash_bits=16, chain_depth=16,
+               window_log2=0, lit_lanes=64, seq_lanes=16, prob_bits=(11, 10, 10, 10), level_penalty=8)
+
+
+def test_split_container_identical_to_oracle(have_lib):
+    """lz_encode_split writes the stream-separated container of the oracle's
+    plain definition byte for byte (also with no records at all)."""
+    import oracle.split as sp
+    from gen.fastq import fastq
+    x, _ = fastq(n_records=500, seed=21)
+    x = bytes(x)
+    assert lz.encode_split(x, **SPLIT_P) == sp.encode(x, **SPLIT_P)
+    assert lz.encode_split(x, threads=3, **SPLIT_P) == sp.encode(x, **SPLIT_P)
+    assert lz.encode_split(b"", **SPLIT_P) == sp.encode(b"", **SPLIT_P)
+
+
+def test_split_encoder_refuses_what_the_definition_refuses(have_lib):
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "split_fastq.json")))
+    for text in g["rejected"]:
+        with pytest.raises(lz.LzError) as e:
+            lz.encode_split(text.encode(), **SPLIT_P)
+        assert e.value.code == -1, text
