@@ -368,6 +368,83 @@ def big_genome_leg(args, dev):
             pass
 
 
+def split_leg(x: bytes, a_mono: bytes, args, dev, threads: int, steps: int = 10) -> dict:
+    """Stream-separated FASTQ container of the same file (ids, sequences, '+'
+    lines and qualities as four archives, Discussion: "Where ACEAPEX Stands
+    on Ratio"): ratio against the monolithic archive, whole-file decode rate
+    (four stream decodes plus the device reassembly, bit-exact), one read and
+    a 1 MiB range."""
+    import numpy as np
+    import torch
+    import paper_2606_18900_amd as lz
+    t0 = time.time()
+    cached = os.path.join(args.cache, "fastq_%d_seed2.lzsf" % args.bytes) if args.cache else None
+    if cached and os.path.exists(cached):
+        with open(cached, "rb") as f:
+            c = f.read()
+    else:
+        c = lz.encode_split(x, threads=threads, **FASTQ_PARAMS)
+        if cached:
+            with open(cached, "wb") as f:
+                f.write(c)
+    enc_s = time.time() - t0
+    sa = lz.SplitArchive(c, device=dev)
+    N = sa.n
+    out = torch.empty(N + 256, dtype=torch.uint8, device=dev)
+    sa.decode_all(out)
+    torch.cuda.synchronize()
+    sa.sync_status()
+    ok = bool(np.array_equal(out[:N].cpu().numpy(), np.frombuffer(x, dtype=np.uint8)))
+    if not ok:
+        raise RuntimeError("split container: decoded file differs from the source")
+    for _ in range(2):
+        sa.decode_all(out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        sa.decode_all(out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    # one read, one 1 MiB range (device time, median of 50)
+    ids = torch.tensor([sa.n_reads // 3], dtype=torch.int64, device=dev)
+    rout = torch.empty(int(sa.info.max_record_len) + 256, dtype=torch.uint8, device=dev)
+    roffs = torch.empty(2, dtype=torch.int64, device=dev)
+    rsc = torch.empty(sa.scratch_bytes(1), dtype=torch.uint8, device=dev)
+    mout = torch.empty(1 << 20, dtype=torch.uint8, device=dev)
+
+    def med(fn):
+        ts = []
+        for _ in range(50):
+            b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            b0.record()
+            fn()
+            b1.record()
+            torch.cuda.synchronize()
+            ts.append(b0.elapsed_time(b1) * 1e3)
+        return round(float(np.median(ts)), 1)
+    read_us = med(lambda: sa.read_lookup(ids, out=rout, offsets=roffs, scratch=rsc))
+    range_us = med(lambda: sa.decode_range(N // 2, 1 << 20, out=mout, scratch=rsc))
+    sa.sync_status()
+    streams = [int(v) for v in sa.info.archive_len]
+    tables = len(c) - sum(streams)
+    res = {
+        "container_bytes": len(c), "ratio": round(N / len(c), 4),
+        "monolithic_bytes": len(a_mono), "monolithic_ratio": round(N / len(a_mono), 4),
+        "smaller_by_pct": round(100.0 * (1 - len(c) / len(a_mono)), 2),
+        "stream_archive_bytes": dict(zip("HSPQ", streams)), "index_and_padding_bytes": tables,
+        "encode_s": round(enc_s, 1), "decode_ms": round(ms, 3), "decode_gbps": round(N / ms / 1e6, 1),
+        "bit_exact": ok, "read_p50_us": read_us, "range_1mib_p50_us": range_us,
+    }
+    log("split FASTQ container: %d bytes (ratio %.3f vs monolithic %.3f, %.1f%% smaller); decode %.3f ms "
+        "= %.1f GB/s bit-exact; one read %.0f us, 1 MiB range %.0f us"
+        % (len(c), N / len(c), N / len(a_mono), res["smaller_by_pct"], ms, res["decode_gbps"], read_us, range_us))
+    sa.close()
+    del sa, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def serving(arq, starts, dev, duration_s: float = 1.0, limit_s: float = 10.0) -> dict:
     """Served decode loop over the resident FASTQ archive and a 2 GiB genome
     archive: open-loop Poisson traces at 2k, 20k and 200k requests/s (90 %
@@ -459,7 +536,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--bytes", type=int, default=1 << 30, help="FASTQ size (default 1 GiB)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", choices=("all", "decode", "copy", "serve", "genome", "biggenome", "reads"),
+    ap.add_argument("--legs", choices=("all", "decode", "copy", "serve", "genome", "biggenome", "reads",
+                                       "split"),
                     default="all",
                     help="decode: only the whole-file decode in the reported launch mode "
                          "(for profiling; no range leg, no CPU baseline); copy: a plain "
@@ -553,6 +631,9 @@ def main() -> int:
 
     if args.stage_clocks:
         return stage_clocks(arc, out)
+    if args.legs == "split":
+        print(json.dumps({"split_fastq": split_leg(x, a, args, dev, threads)}), flush=True)
+        return 0
 
     def run(mode: int, wg: int, steps: int, warmup: int):
         arc.set_tuning(sync_mode=mode, wg_per_cu=wg)
@@ -578,8 +659,8 @@ def main() -> int:
         arc.set_tuning(sync_mode=0, wg_per_cu=3)
         print(json.dumps({"read_access_us": read_latency(arc, starts, 200, dev)}), flush=True)
         return 0
-    # both launch modes: one launch per dependency level, and one persistent
-    # launch whose workgroups wait on per-block completion flags
+    # both launch modes: one launch per dependency level, and one cooperative
+    # launch whose workgroups walk the levels with a grid barrier between them
     modes = {}
     for mode, name in (((0, "per-level launches"),) if args.legs == "decode" else
                        ((0, "per-level launches"), (1, "persistent"))):
@@ -593,7 +674,7 @@ def main() -> int:
     value = N * args.steps / wall / 1e9
     kern_ms = float(np.mean(ms))
     launch = ("one launch per dependency level, 3 workgroups/CU" if best == 0
-              else "persistent, 3 workgroups/CU, per-block completion flags")
+              else "persistent, 3 workgroups/CU, grid barrier per level")
     log("reported: %s, %.3f ms/step wall, %.1f GB/s" % (launch, ms_step, value))
     arc.set_tuning(sync_mode=best, wg_per_cu=3)
 
@@ -650,6 +731,10 @@ def main() -> int:
     served = None
     if args.legs == "all":
         served = serving(arc, starts, dev)
+
+    split = None
+    if args.legs == "all":
+        split = split_leg(x, a, args, dev, threads)
 
     # algorithmic bytes of one decode: compressed payload + directory +
     # dependency lists read, match-source bytes, output bytes
@@ -723,6 +808,7 @@ def main() -> int:
         "end_to_end_pcie": e2e,
         "batched_lookups": batch_res,
         "serving": served,
+        "split_fastq": split,
         "encode_s": round(enc_s, 1),
     }
     print(json.dumps(line), flush=True)

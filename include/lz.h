@@ -93,12 +93,19 @@ typedef struct lz_request {
 
 /* Launch knobs (chosen by the autotuner; none of them changes a decoded byte). */
 typedef struct lz_tuning {
-  uint32_t sync_mode;   /* 0 = per-level launches (lz_open's default), 1 = one
-                           persistent launch with per-block completion flags */
+  uint32_t sync_mode;   /* whole-file decode: 0 = one launch per dependency
+                           level (lz_open's default), 1 = one cooperative
+                           launch with a grid barrier between levels      */
   uint32_t wg_per_cu;   /* grid = wg_per_cu * CUs workgroups (a level launch
                            takes at most its block count); 1..4, default 3   */
   uint32_t spin_limit;  /* watchdog: max polls of a dependency flag before the
                            kernel gives up with LZ_ECORRUPT (0 = default)     */
+  uint32_t req_sync_mode; /* request calls (ranges, reads, batches): the same
+                           two modes for the closure decode; default 0     */
+  uint32_t plan_blocks; /* request calls expected to cover at most this many
+                           blocks are planned by one workgroup in one launch,
+                           larger ones by the eight-kernel path; 1..2^20, 0 =
+                           default 4096                                     */
 } lz_tuning;
 
 typedef struct lz_handle lz_handle;

@@ -5,4 +5,4 @@ from ._lib import LzError, lib  # noqa: F401
 from .archive import Archive, SplitArchive, encode, encode_split, fasta_index, info  # noqa: F401
 from .batch import Batcher  # noqa: F401
 from .serve import Server  # noqa: F401,E402
-from .tune import tune  # noqa: F401,E402
+from .tune import tune, tune_encoding, tune_requests  # noqa: F401,E402

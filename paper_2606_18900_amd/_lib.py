@@ -73,7 +73,8 @@ class SplitInfo(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("sync_mode", C.c_uint32), ("wg_per_cu", C.c_uint32), ("spin_limit", C.c_uint32)]
+    _fields_ = [("sync_mode", C.c_uint32), ("wg_per_cu", C.c_uint32), ("spin_limit", C.c_uint32),
+                ("req_sync_mode", C.c_uint32), ("plan_blocks", C.c_uint32)]
 
 
 _lib = None

@@ -120,14 +120,13 @@ class Archive:
         return t
 
     def set_tuning(self, sync_mode: int | None = None, wg_per_cu: int | None = None,
-                   spin_limit: int | None = None):
+                   spin_limit: int | None = None, req_sync_mode: int | None = None,
+                   plan_blocks: int | None = None):
         t = self.tuning()
-        if sync_mode is not None:
-            t.sync_mode = sync_mode
-        if wg_per_cu is not None:
-            t.wg_per_cu = wg_per_cu
-        if spin_limit is not None:
-            t.spin_limit = spin_limit
+        for f, v in (("sync_mode", sync_mode), ("wg_per_cu", wg_per_cu), ("spin_limit", spin_limit),
+                     ("req_sync_mode", req_sync_mode), ("plan_blocks", plan_blocks)):
+            if v is not None:
+                setattr(t, f, v)
         check(lib().lz_set_tuning(self.h, C.byref(t)))
 
     # -- decode

@@ -1958,12 +1958,12 @@ int lz_launch_requests(lz_handle* h, const lz_request* d_reqs, const uint32_t* d
   const uint32_t spin = h->tune.spin_limit ? h->tune.spin_limit : (1u << 20);
   const uint32_t g_req = (uint32_t)std::min<uint64_t>(1024, (n_max + 255) / 256);
   // small calls are planned by one workgroup (one launch instead of eight):
-  // at most 4096 covering blocks expected (a range, reads at two blocks each,
-  // batches of up to 16 requests)
-  const uint64_t Bs = 1ull << v.block_log2;
-  const bool small = R.mode == 0 ? single_len / Bs + 2 <= 4096
-                   : R.mode == 1 ? n_max * (v.max_record_len / Bs + 2) <= 4096
-                                 : n_max <= 16;
+  // at most plan_blocks covering blocks expected (a range, reads at two
+  // blocks each, batches at 256 blocks a request)
+  const uint64_t Bs = 1ull << v.block_log2, pb = h->tune.plan_blocks ? h->tune.plan_blocks : 4096;
+  const bool small = R.mode == 0 ? single_len / Bs + 2 <= pb
+                   : R.mode == 1 ? n_max * (v.max_record_len / Bs + 2) <= pb
+                                 : n_max * 256 <= pb;
   const uint32_t g_wide = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(1024, (v.n_blocks + 255) / 256));
   if (small) {
     hipLaunchKernelGGL(k_req_plan, dim3(1), dim3(kPlanWG), 0, s, R);
@@ -1986,7 +1986,7 @@ int lz_launch_requests(lz_handle* h, const lz_request* d_reqs, const uint32_t* d
   const uint32_t slots = (uint32_t)(h->n_cu * std::max(1u, h->tune.wg_per_cu));
   const uint32_t grid = (uint32_t)std::min<uint64_t>(slots, std::max<uint64_t>(1, v.n_blocks));
   bool done = false;
-  if (h->tune.sync_mode == 1) {
+  if (h->tune.req_sync_mode == 1) {
     const int rc = launch_persistent(h, A, s, &done);
     if (rc) return rc;
   }

@@ -267,6 +267,8 @@ extern "C" int lz_open(const uint8_t* d_archive, uint64_t len, void* d_ws, uint6
   h->tune.sync_mode = 0;
   h->tune.wg_per_cu = 3;
   h->tune.spin_limit = 0;
+  h->tune.req_sync_mode = 0;
+  h->tune.plan_blocks = 4096;
   int dev = 0;
   hipDeviceProp_t prop;
   rc = hip_check(hipGetDevice(&dev), "lz_open: device");
@@ -324,8 +326,10 @@ extern "C" int lz_get_info(const lz_handle* h, lz_info* out) {
 
 extern "C" int lz_set_tuning(lz_handle* h, const lz_tuning* t) {
   if (!h || !t) return lz_fail(LZ_EINVAL, "lz_set_tuning: null");
-  if (t->sync_mode > 1 || t->wg_per_cu < 1 || t->wg_per_cu > 4) return lz_fail(LZ_EINVAL, "lz_set_tuning: out of range");
+  if (t->sync_mode > 1 || t->wg_per_cu < 1 || t->wg_per_cu > 4 || t->req_sync_mode > 1 || t->plan_blocks > (1u << 20))
+    return lz_fail(LZ_EINVAL, "lz_set_tuning: out of range");
   h->tune = *t;
+  if (!h->tune.plan_blocks) h->tune.plan_blocks = 4096;
   return LZ_OK;
 }
 

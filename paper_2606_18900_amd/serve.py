@@ -78,7 +78,7 @@ class Server:
                     import torch
                     from .archive import Archive
                     h = Archive(arc.d_archive, device=arc.device)     # own workspace
-                    h.set_tuning(**{f: getattr(arc.tuning(), f) for f in ("sync_mode", "wg_per_cu")})
+                    h.set_tuning(**{f: getattr(arc.tuning(), f) for f in ("sync_mode", "wg_per_cu", "req_sync_mode", "plan_blocks")})
                     lane.append(batcher(h, self.n_max, self.window, n_slots=arc.n_blocks,
                                         use_graph=use_graph, stream=torch.cuda.Stream(device=arc.device)))
                 else:

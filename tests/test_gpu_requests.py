@@ -72,7 +72,7 @@ def _diagnose(arc):
 
 
 def _range(arc, o, L, mode=1):
-    arc.set_tuning(sync_mode=mode)
+    arc.set_tuning(sync_mode=mode, req_sync_mode=mode)
     out = torch.empty(max(L, 1) + 64, dtype=torch.uint8, device="cuda")
     scratch = torch.full((arc.scratch_bytes(1),), 0xAA, dtype=torch.uint8, device="cuda")
     arc.decode_range(o, L, out=out, scratch=scratch)
@@ -119,7 +119,7 @@ def test_read_lookup_all_reads(fq):
     x, starts, arc = fq
     n = len(starts) - 1
     for mode in (1, 0):
-        arc.set_tuning(sync_mode=mode)
+        arc.set_tuning(sync_mode=mode, req_sync_mode=mode)
         ids = np.arange(n, dtype=np.int64)
         out, offs = arc.read_lookup(ids)
         _sync(arc)
@@ -168,7 +168,7 @@ def test_batch_mixed_equals_singles(fq):
             o = int(rng.integers(0, len(x) - 1))
             reqs.append((1, o, int(min(len(x) - o, rng.integers(1, 100000)))))
     for mode in (1, 0):
-        arc.set_tuning(sync_mode=mode)
+        arc.set_tuning(sync_mode=mode, req_sync_mode=mode)
         got = _batch(arc, reqs, n_max=512)
         for (kind, a, b), g in zip(reqs, got):
             exp = x[int(starts[a]):int(starts[a + 1])] if kind == 0 else x[a:a + b]
@@ -204,7 +204,7 @@ def test_batcher_graph_replays(fq):
     the eager (ungraphed) result and the plain definition."""
     from paper_2606_18900_amd.batch import Batcher
     x, starts, arc = fq
-    arc.set_tuning(sync_mode=1)
+    arc.set_tuning(sync_mode=1, req_sync_mode=1)
     rng = np.random.default_rng(5)
     g = Batcher(arc, n_max=256, out_cap=8 << 20, use_graph=True)
     e = Batcher(arc, n_max=256, out_cap=8 << 20, use_graph=False)
@@ -246,7 +246,7 @@ def test_stream_range_windows_reach_evicted_blocks(orc, small):
         reach += closure > covering
     assert reach >= 3
     for mode in (1, 0):
-        arc.set_tuning(sync_mode=mode)
+        arc.set_tuning(sync_mode=mode, req_sync_mode=mode)
         wbuf = torch.full((win + 64,), 0x55, dtype=torch.uint8, device="cuda")
         scratch = torch.full((arc.scratch_bytes(1),), 0xAA, dtype=torch.uint8, device="cuda")
         n_win = 0
@@ -270,7 +270,7 @@ def test_range_with_swapped_dependency_is_corrupt(orc, lz):
     arc = lz.Archive(t)
     B = 1 << 14
     for mode in (1, 0):
-        arc.set_tuning(sync_mode=mode)
+        arc.set_tuning(sync_mode=mode, req_sync_mode=mode)
         # decode the wrongly omitted block first, so its address-table entry
         # holds a pointer from an earlier call
         assert _range(arc, d * B, 100, mode) == x[d * B:d * B + 100]
