@@ -127,6 +127,20 @@ def parse(data, **kw):
     return res
 
 
+def rebase(parsed: dict, block_log2: int) -> np.ndarray:
+    """Sources after the encoder's rebasing step (orc_rebase) applied to a
+    parse as returned by parse(); returns the new offsets."""
+    of = np.ascontiguousarray(parsed["of"], dtype=np.uint64).copy()
+    blk = np.ascontiguousarray(parsed["blk"], dtype=np.uint32)
+    ll = np.ascontiguousarray(parsed["ll"], dtype=np.uint32)
+    ml = np.ascontiguousarray(parsed["ml"], dtype=np.uint32)
+    n = len(of)
+    if n:
+        lib().orc_rebase(C.c_uint64(n), C.c_void_p(blk.ctypes.data), C.c_void_p(ll.ctypes.data),
+                         C.c_void_p(ml.ctypes.data), C.c_void_p(of.ctypes.data), C.c_uint32(block_log2))
+    return of
+
+
 def info(archive: bytes) -> Info:
     a, p = _buf(archive)
     i = Info()

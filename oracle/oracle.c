@@ -506,6 +506,56 @@ int orc_parse(const uint8_t* src, uint64_t n, const orc_params* p, uint64_t* n_s
   return ORC_OK;
 }
 
+/* ---------------------------------------------------------- rebasing
+ * An encoder choice the format leaves free (any source position holding the
+ * same bytes decodes alike): a match that does not overlap itself and whose
+ * source window [o, o + M) lies wholly inside the destination of an earlier
+ * match of the same block -- one that does not overlap itself either, so its
+ * destination equals its source byte for byte -- takes its bytes from that
+ * match's source instead: o becomes o_c + (o - p_c).  This is repeated until
+ * no such match holds the window (each step moves to a match of smaller
+ * index, so it ends).  Matches are handled in sequence order, so an earlier
+ * match's source is already final.  The window moves into a region the block
+ * already depends on, so dependencies and levels do not change; in-block
+ * copy chains get shorter.  Applied to the sequences of blocks [0, nb). */
+void orc_rebase(uint64_t n_seq, const uint32_t* blk, const uint32_t* ll, const uint32_t* ml,
+                uint64_t* of, uint32_t block_log2) {
+  uint64_t i = 0;
+  uint64_t* pd = (uint64_t*)malloc((n_seq ? n_seq : 1) * 8);   /* destinations of the block's matches */
+  uint64_t* ix = (uint64_t*)malloc((n_seq ? n_seq : 1) * 8);   /* their sequence indexes */
+  while (i < n_seq) {
+    uint64_t j = i;
+    while (j < n_seq && blk[j] == blk[i]) j++;
+    uint64_t pos = (uint64_t)blk[i] << block_log2, nm = 0;
+    for (uint64_t q = i; q < j; q++) {
+      pos += ll[q];
+      if (ml[q]) { pd[nm] = pos; ix[nm] = q; nm++; }
+      pos += ml[q];
+    }
+    for (uint64_t m = 0; m < nm; m++) {
+      const uint64_t q = ix[m], p = pd[m], M = ml[q];
+      for (;;) {
+        const uint64_t o = of[q];
+        if (p - o < M) break;                       /* overlaps itself */
+        /* the last earlier match whose destination starts at or before o */
+        uint64_t lo = 0, hi = m;                     /* answer in [0, m): first with pd > o, minus one */
+        while (lo < hi) {
+          const uint64_t mid = (lo + hi) / 2;
+          if (pd[mid] <= o) lo = mid + 1; else hi = mid;
+        }
+        if (lo == 0) break;
+        const uint64_t c = lo - 1, qc = ix[c], pc = pd[c], Mc = ml[qc], oc = of[qc];
+        if (o + M > pc + Mc) break;                 /* window not inside its destination */
+        if (pc - oc < Mc) break;                    /* it overlaps itself */
+        of[q] = oc + (o - pc);
+      }
+    }
+    i = j;
+  }
+  free(pd);
+  free(ix);
+}
+
 /* -------------------------------------------------------------- streams
  * Four streams per block (Background section): CMD = literal-run lengths,
  * MLEN = match lengths, OFF = absolute source offsets, LIT = literal bytes.
@@ -608,6 +658,7 @@ int orc_encode(const uint8_t* x, uint64_t n, const orc_params* pr,
   parse_t ps;
   rc = do_parse(x, n, pr, &ps);
   if (rc) { free(ridx); return rc; }
+  orc_rebase(ps.seq.n, ps.seq.blk, ps.seq.ll, ps.seq.ml, ps.seq.of, pr->block_log2);
 
   /* per-block sequence ranges */
   uint64_t* sptr = (uint64_t*)calloc(nb + 1, 8);

@@ -67,6 +67,9 @@ int orc_rans_decode(const uint8_t* body, uint64_t body_len, uint32_t n,
 
 /* Parse only: the greedy hash-chain parse with the level cap.  Returns arrays
  * (owned by the caller, free with orc_free) of n_seq entries: block id, LL, ML, OF. */
+/* Source rebasing of a parse (see oracle.c), in place on `of`. */
+void orc_rebase(uint64_t n_seq, const uint32_t* blk, const uint32_t* ll, const uint32_t* ml,
+                uint64_t* of, uint32_t block_log2);
 int orc_parse(const uint8_t* src, uint64_t n, const orc_params* p,
               uint64_t* n_seq, uint32_t** blk, uint32_t** ll, uint32_t** ml,
               uint64_t** of, uint16_t** level);

@@ -639,6 +639,41 @@ void parallel_for(uint64_t n, unsigned threads, F&& f) {
   for (auto& t : ts) t.join();
 }
 
+// Source rebasing, an encoder choice the format leaves free: a match that
+// does not overlap itself and whose source window lies wholly inside the
+// destination of an earlier match of its block (one not overlapping itself,
+// so that destination equals its source byte for byte) reads from that
+// match's source instead; repeated until no match holds the window (each
+// step goes to a match of smaller index).  Matches are taken in sequence
+// order, so earlier sources are final.  The window moves into bytes the block
+// already depends on: dependencies and levels stay; in-block copy chains, and
+// the decoder's dependency passes, get shorter.  Blocks are independent.
+void rebase_sources(Parse& ps, uint64_t nb, uint32_t bl, unsigned threads) {
+  parallel_for(nb, threads, [&](uint64_t b, unsigned) {
+    const uint64_t s0 = ps.seq_ptr[b], s1 = ps.seq_ptr[b + 1];
+    std::vector<uint64_t> dst, idx;             // the block's matches: destination, sequence index
+    uint64_t pos = b << bl;
+    for (uint64_t q = s0; q < s1; q++) {
+      pos += ps.ll[q];
+      if (ps.ml[q]) { dst.push_back(pos); idx.push_back(q); }
+      pos += ps.ml[q];
+    }
+    for (uint64_t m = 0; m < dst.size(); m++) {
+      const uint64_t q = idx[m], p = dst[m], M = ps.ml[q];
+      for (;;) {
+        const uint64_t o = ps.of[q];
+        if (p - o < M) break;                                    // overlaps itself
+        // the last earlier match whose destination starts at or before o
+        const uint64_t c1 = (uint64_t)(std::upper_bound(dst.begin(), dst.begin() + m, o) - dst.begin());
+        if (!c1) break;
+        const uint64_t c = c1 - 1, qc = idx[c], pc = dst[c], Mc = ps.ml[qc], oc = ps.of[qc];
+        if (o + M > pc + Mc || pc - oc < Mc) break;              // not inside, or it overlaps itself
+        ps.of[q] = oc + (o - pc);
+      }
+    }
+  });
+}
+
 int check(const lz_params& p) {
   if (p.block_log2 < 6 || p.block_log2 > 15) return LZ_EINVAL;
   if (p.max_level < 1 || p.max_level > 64) return LZ_EINVAL;
@@ -717,6 +752,7 @@ extern "C" int lz_encode(const uint8_t* x, uint64_t n, const lz_params* pp, uint
            : n < (1ull << 32) - 1 ? parse_impl<uint32_t>(x, n, pr, threads, ps)
                                   : parse_impl<uint64_t>(x, n, pr, threads, ps);
   if (rc) return lz_fail(rc, "lz_encode: parse failed");
+  rebase_sources(ps, nb, bl, threads);
 
   // per-block stream bytes, built on demand
   auto build = [&](uint64_t b, std::vector<uint8_t> s[4]) {
