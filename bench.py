@@ -98,7 +98,9 @@ def batched_lookups_leg(arc, starts, N, dev, log, src):
     """2^20 mixed requests (90 % reads, 10 % ranges of 4 KiB..1 MiB) served in
     batches through one captured HIP graph per batch size; each batch is
     copied in, replayed and waited for.  Batch size 1 without a graph is the
-    one-launch-sequence-per-request baseline (run on the first 4096 requests)."""
+    one-launch-sequence-per-request baseline (run on the first 4096 requests);
+    batches of 256 and 4096 are also run with the closure decoded by one
+    cooperative launch (eager)."""
     import numpy as np
     import torch
     from gen.requests import batched_lookups
@@ -107,8 +109,13 @@ def batched_lookups_leg(arc, starts, N, dev, log, src):
     rec = np.diff(starts)
     nbytes = np.where(kind == 0, rec[np.minimum(a, len(rec) - 1)], b)
     res = {}
-    for bs, use_graph, limit in ((1, False, 4096), (1, True, 4096), (16, True, 1 << 16),
-                                 (256, True, 1 << 20), (4096, True, 1 << 20)):
+    # (batch size, graph, requests, closure decode mode): per-level launches
+    # captured in graphs, and one cooperative launch per batch (eager: a
+    # cooperative launch is not captured)
+    for bs, use_graph, limit, persist in ((1, False, 4096, 0), (1, True, 4096, 0), (16, True, 1 << 16, 0),
+                                          (256, True, 1 << 20, 0), (4096, True, 1 << 20, 0),
+                                          (256, False, 1 << 18, 1), (4096, False, 1 << 20, 1)):
+        arc.set_tuning(req_sync_mode=persist)
         n_req = min(limit, len(kind))
         nb = n_req // bs
         cap = int(max(nbytes[q * bs:(q + 1) * bs].sum() for q in range(nb)))
@@ -128,12 +135,13 @@ def batched_lookups_leg(arc, starts, N, dev, log, src):
             o = int(starts[a[r]]) if kind[r] == 0 else int(a[r])
             if got[j] != src[o:o + int(nbytes[r])]:
                 raise RuntimeError("batched lookup mismatch (batch size %d, request %d)" % (bs, r))
-        key = "batch%d%s" % (bs, "" if use_graph else "_eager")
+        key = "batch%d%s" % (bs, "_persistent" if persist else ("" if use_graph else "_eager"))
         res[key] = {"requests": nb * bs, "req_per_s": round(nb * bs / wall, 1),
                     "GB_per_s": round(float(nbytes[:nb * bs].sum()) / wall / 1e9, 3),
                     "batch_p50_us": pct(lat, 50), "batch_p99_us": pct(lat, 99)}
         log("batched lookups %s: %s" % (key, res[key]))
         del bt
+    arc.set_tuning(req_sync_mode=0)
     return res
 
 
