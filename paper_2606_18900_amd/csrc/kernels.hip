@@ -101,7 +101,8 @@ struct Smem {
   uint32_t pok;                // prepared block: records valid
   uint32_t dummy[64];          // target of the masked-off lanes' byte stores
   uint32_t scan[3][kWaves];
-  uint32_t item, err, perr, next, nin;
+  uint32_t perr[3];            // prepared block: short stream k failed its checks
+  uint32_t item, err, next, nin;
 #ifdef LZ_STAGE_CLOCKS
   uint64_t clk[kClkSlots], clk_last;
 #endif
@@ -590,7 +591,7 @@ __device__ __forceinline__ void put_prep(Smem& S, const BlockDir& d, const Strea
 // and OFF streams are decoded into the sequence tables.  The literal record
 // goes to S.pst with the directory fields and literal group word ranges
 // (put_prep), the outcome to S.pok; a short stream that fails its checks sets
-// S.perr.
+// S.perr[k] (written by the wave that decoded stream k, 0 or 1).
 //
 // prep_tile: all four waves.  The first min(plen, 16 KiB) payload bytes go
 // into the tile (free until the literal stage) with one round of 16-byte
@@ -608,7 +609,7 @@ __device__ void prep_tile(Smem& S, const DevArgs& A, uint32_t b) {
     for (uint32_t c = t; c < (hlen >> 4); c += kWG) dst4[c] = src4[c];
     if (t < (hlen & 15u)) S.tile[(hlen & ~15u) + t] = pay[(hlen & ~15u) + t];
   }
-  if (t == 0) { S.perr = 0; S.next = 0; }
+  if (t == 0) S.next = 0;
   __syncthreads();
   CLK_MARK(S, 0);
   Stream sc, sm, so, sl;
@@ -621,7 +622,8 @@ __device__ void prep_tile(Smem& S, const DevArgs& A, uint32_t b) {
   CLK_MARK(S, 1);
   if (ok && wv < 3) {
     const Stream& s = wv == 0 ? sc : (wv == 1 ? sm : so);
-    if (!short_stream(S, A, wv, s, S.tile, d.ns) && lane == 0) S.perr = 1;
+    const bool okw = short_stream(S, A, wv, s, S.tile, d.ns);
+    if (lane == 0) S.perr[wv] = okw ? 0u : 1u;
   }
   __syncthreads();
   CLK_MARK(S, 2);
@@ -656,7 +658,7 @@ __device__ void prep_ring(Smem& S, const DevArgs& A, uint32_t b) {
     const Stream& s = role == 0 ? sc : (role == 1 ? sm : so);
     okw = short_stream(S, A, role, s, S.prep, d.ns);
   }
-  if (!okw && lane == 0) S.perr = 1;
+  if (ok && lane == 0) S.perr[wv - 1] = okw ? 0u : 1u;
   if (wv == 1 && lane == 0) {
     S.pok = ok ? 1u : 0u;
     put_prep(S, d, sl, S.prep, ok);
@@ -732,6 +734,14 @@ __device__ bool decode_block(Smem& S, const DevArgs& A, uint32_t b, uint32_t nb)
             S.lst[atomicAdd(&S.next, 1u)] = (uint16_t)j;   // from earlier blocks, any order
           } else {
             S.lst[kMaxSeq - 1 - pin] = (uint16_t)j;        // in-block, in sequence order
+            if (pin < 64) {                                // the common case: its fields at once
+              const uint32_t d0 = po + ll[q];
+              const uint64_t dabs = sb + d0;
+              S.fdst[pin] = (uint16_t)d0;
+              S.flen[pin] = (uint16_t)min(ml[q], blen);
+              S.fpk[pin] = ((uint32_t)((int64_t)of - (int64_t)sb + 16384) & 0xFFFFu) |
+                           ((dabs > of ? (uint32_t)min<uint64_t>(dabs - of, 32767) : 1u) << 16);
+            }
             pin++;
           }
         }
@@ -747,7 +757,7 @@ __device__ bool decode_block(Smem& S, const DevArgs& A, uint32_t b, uint32_t nb)
     if (bad) S.err = 1;
   }
   __syncthreads();
-  if (S.err || S.perr) {
+  if (S.err || S.perr[0] || S.perr[1] || S.perr[2]) {
     if (t == 0) latch(A.ctl, kStCorrupt);
     return false;
   }
@@ -865,7 +875,6 @@ __device__ bool decode_block(Smem& S, const DevArgs& A, uint32_t b, uint32_t nb)
     return false;
   }
   CLK_MARK(S, 5);
-  if (t == 0) S.perr = 0;   // every thread has read it (stage 2): free for the next block
 
   // ---- stage 4: matches whose source touches the block itself.
   // With period d = p - OF, out[p+k] = out[OF + (k mod d)] for every k (the
@@ -880,11 +889,11 @@ __device__ bool decode_block(Smem& S, const DevArgs& A, uint32_t b, uint32_t nb)
   //     are done.  Short matches (at most 64 bytes, no overlap with themselves,
   //     source inside the tile) are copied by their own lane from four-byte
   //     words; the others by the whole wave, one at a time.
-  // With at most 64 in-block matches (the common case) their fields go to
-  // their own small arrays and only wave 0 works on them after the first
-  // barrier; the sequence tables are then free, and waves 1..3 prepare the
-  // next block meanwhile.  With more, the fields are packed into the sequence
-  // tables and 4a uses every thread.
+  // With at most 64 in-block matches (the common case) stage 2 has written
+  // their fields to their own small arrays and only wave 0 works on them: the
+  // sequence tables are free, and waves 1..3 prepare the next block
+  // meanwhile.  With more, the fields are packed into the sequence tables and
+  // 4a uses every thread.
   const uint32_t cnt = min(S.nin, ns);
   const bool small = cnt <= 64;
   uint16_t* Fd = small ? S.fdst : S.lit;     // destination
@@ -924,7 +933,7 @@ __device__ bool decode_block(Smem& S, const DevArgs& A, uint32_t b, uint32_t nb)
       }
     }
   };
-  if (cnt) {
+  if (!small) {                              // more than 64: fields packed into the tables
 #pragma unroll
     for (uint32_t u = 0; u < 5; u++) {
       const uint32_t a = a0 + u;
@@ -941,7 +950,7 @@ __device__ bool decode_block(Smem& S, const DevArgs& A, uint32_t b, uint32_t nb)
       ms[u] = (uint32_t)((int64_t)of - (int64_t)sb + 16384) & 0xFFFFu;
       md[u] = dabs > of ? (uint32_t)min<uint64_t>(dabs - of, 32767) : 1u;
     }
-    if (!small) __syncthreads();             // Fd, Fl are the tables just read
+    __syncthreads();                         // Fd, Fl are the tables just read
 #pragma unroll
     for (uint32_t u = 0; u < 5; u++) {
       const uint32_t a = a0 + u;
@@ -950,9 +959,7 @@ __device__ bool decode_block(Smem& S, const DevArgs& A, uint32_t b, uint32_t nb)
         Fl[a] = (uint16_t)mM[u];
       }
     }
-  }
-  __syncthreads();                           // sequence tables read; Fd, Fl written
-  if (cnt && !small) {
+    __syncthreads();
     ranges();
     __syncthreads();
   }
@@ -962,8 +969,15 @@ __device__ bool decode_block(Smem& S, const DevArgs& A, uint32_t b, uint32_t nb)
   const bool ov = small && nb != ~0u;
   const uint64_t c4_ = CLK_NOW();
   if (wv == 0 && cnt) {
-    if (small) {
-      ranges();                              // this wave's own Fd, Fl stores precede
+    if (small) {                             // fields from stage 2 (before two barriers)
+      if (a0 < a1) {
+        const uint32_t pk = Fp[a0];
+        md0[0] = Fd[a0];
+        mM[0] = Fl[a0];
+        ms[0] = pk & 0xFFFFu;
+        md[0] = pk >> 16;
+      }
+      ranges();
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     }
     bool bad = false;
