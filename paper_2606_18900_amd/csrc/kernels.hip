@@ -768,30 +768,30 @@ __device__ bool decode_block(Smem& S, const DevArgs& A, uint32_t b, uint32_t nb)
     bool bad = false;
     const uint32_t nx = min(S.next, ns), slot = lane >> 3, sub = lane & 7;
     // Matches with a source wholly in earlier blocks.  In whole-file mode the
-    // first eight are started before the literal decode, two per wave (one
-    // per half-wave): each lane loads two aligned source words covering eight
-    // bytes of the match's first 256, so the HBM latency is spent decoding;
-    // the bytes are stored after it.  The rest are copied eight per wave at a
-    // time, one per 8-lane slot, each lane every eighth byte, all loads in
-    // flight before the stores.
+    // first sixteen are started before the literal decode, four per wave (one
+    // per 16-lane quarter): each lane loads two aligned source words covering
+    // eight bytes of the match's first 128, so the HBM latency is spent
+    // decoding; the bytes are stored after it.  The rest are copied eight per
+    // wave at a time, one per 8-lane slot, each lane every eighth byte, all
+    // loads in flight before the stores.
     const bool early = A.addr == nullptr;
-    const uint32_t half = lane >> 5, hsub = lane & 31;
+    const uint32_t quarter = lane >> 4, qsub = lane & 15;
     uint32_t pM = 0, pd0 = 0, pw0 = 0, pw1 = 0;
     uint64_t pof = 0, pa = 0;
     if (early) {
-      const uint32_t e = 2 * wv + half;
+      const uint32_t e = 4 * wv + quarter;
       const uint32_t q = e < nx ? min((uint32_t)S.lst[e], ns - 1) : 0u;
       const uint32_t L = (uint32_t)S.lit[q + 1] - S.lit[q];
       pM = e < nx ? (uint32_t)S.out[q + 1] - S.out[q] - L : 0u;
       pof = (uint64_t)S.oflo[q] | ((uint64_t)S.ofhi[q] << 32);
       pd0 = S.out[q] + L;
-      // words [pa, pa + 8) with pa = (of & ~3) + 8 * hsub cover the bytes
-      // k < 256 - (of & 3) of the match; the last word may reach up to 3 bytes
+      // words [pa, pa + 8) with pa = (of & ~3) + 8 * qsub cover the bytes
+      // k < 128 - (of & 3) of the match; the last word may reach up to 3 bytes
       // past the match, still inside the output (the source ends at or
       // before this block's start)
-      pa = (pof & ~3ull) + 8ull * hsub;
+      pa = (pof & ~3ull) + 8ull * qsub;
       const uint32_t* w = reinterpret_cast<const uint32_t*>(A.out + pa);
-      const uint64_t lim = pof + min(pM, 256u - (uint32_t)(pof & 3));
+      const uint64_t lim = pof + min(pM, 128u - (uint32_t)(pof & 3));
       pw0 = pa < lim ? w[0] : 0u;
       pw1 = pa + 4 < lim ? w[1] : 0u;
     }
@@ -821,26 +821,26 @@ __device__ bool decode_block(Smem& S, const DevArgs& A, uint32_t b, uint32_t nb)
     }
     CLK_MARK(S, 4);
     if (early) {
-      const uint64_t lim = pof + min(pM, 256u - (uint32_t)(pof & 3));
+      const uint64_t lim = pof + min(pM, 128u - (uint32_t)(pof & 3));
 #pragma unroll
       for (uint32_t u = 0; u < 8; u++) {
         const uint64_t a = pa + u;
         const uint32_t v = (u < 4 ? pw0 : pw1) >> (8 * (u & 3));
         if (a >= pof && a < lim) S.tile[pd0 + (uint32_t)(a - pof)] = (uint8_t)v;
       }
-      for (uint32_t k0 = 256u - (uint32_t)(pof & 3); __ballot(k0 < pM); k0 += 256) {   // the rest
+      for (uint32_t k0 = 128u - (uint32_t)(pof & 3); __ballot(k0 < pM); k0 += 128) {   // the rest
         uint32_t v[8];
-        const uint8_t* p = A.out + pof + k0 + hsub;
+        const uint8_t* p = A.out + pof + k0 + qsub;
 #pragma unroll
-        for (uint32_t u = 0; u < 8; u++) v[u] = k0 + hsub + 32 * u < pM ? (uint32_t)p[32 * u] : 0u;
+        for (uint32_t u = 0; u < 8; u++) v[u] = k0 + qsub + 16 * u < pM ? (uint32_t)p[16 * u] : 0u;
 #pragma unroll
         for (uint32_t u = 0; u < 8; u++) {
-          const uint32_t k = k0 + hsub + 32 * u;
+          const uint32_t k = k0 + qsub + 16 * u;
           if (k < pM && pd0 + k < blen) S.tile[pd0 + k] = (uint8_t)v[u];
         }
       }
     }
-    for (uint32_t g0 = 8 * wv + (early ? 2 * kWaves : 0u); g0 < nx; g0 += 8 * kWaves) {
+    for (uint32_t g0 = 8 * wv + (early ? 4 * kWaves : 0u); g0 < nx; g0 += 8 * kWaves) {
       const uint32_t e = g0 + slot;
       const uint32_t q = e < nx ? min((uint32_t)S.lst[e], ns - 1) : 0u;
       const uint32_t L = (uint32_t)S.lit[q + 1] - S.lit[q];
