@@ -469,7 +469,8 @@ __device__ void block_scan3(Smem& S, const uint32_t v[3], uint32_t pre[3], uint3
     pre[f] = base + incl[f] - v[f];
     tot[f] = all;
   }
-  __syncthreads();
+  // no closing barrier: S.scan is next written by the next block's scan,
+  // many barriers later
 }
 
 // Small-stream symbol lookup: binary search of slot u in a 257-entry
@@ -692,8 +693,11 @@ __device__ bool decode_block(Smem& S, const DevArgs& A, uint32_t b, uint32_t nb)
   // ---- stage 2: command placement.  One block scan of (LL, LL + ML,
   // in-block match) counts gives literal and output positions and the order
   // of the in-block matches; the block's sequence invariants are checked.
-  // Values are u16 and ns <= 1025, so no sum reaches 2^32.
-  {
+  // Values are u16 and ns <= 1025, so no sum reaches 2^32.  A block of at
+  // most 64 sequences is placed by wave 0 alone with one wave scan (no
+  // workgroup barrier); waves 1..3 wait at the stage's closing barrier.
+  const bool one = ns <= 64;
+  if (!one || wv == 0) {
     const uint32_t per = (ns + kWG - 1) / kWG;   // <= 5
     const uint32_t j0 = min(ns, t * per), j1 = min(ns, j0 + per);
     uint32_t ll[5], ml[5];
@@ -714,7 +718,16 @@ __device__ bool decode_block(Smem& S, const DevArgs& A, uint32_t b, uint32_t nb)
       v[2] += inb;
     }
     uint32_t pre[3], tot[3];
-    block_scan3(S, v, pre, tot);
+    if (one) {
+#pragma unroll
+      for (int f = 0; f < 3; f++) {
+        const uint32_t incl = wave_scan(v[f]);
+        pre[f] = incl - v[f];
+        tot[f] = __builtin_amdgcn_readlane(incl, 63);
+      }
+    } else {
+      block_scan3(S, v, pre, tot);
+    }
     const uint32_t tl = tot[0], to = tot[1];
     bad |= tl != nlit || to != blen;
     uint32_t pl = pre[0], po = pre[1];
