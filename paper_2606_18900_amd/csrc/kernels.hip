@@ -1858,10 +1858,15 @@ __global__ void __launch_bounds__(kPlanWG) k_req_plan(ReqArgs R) {
     push((uint32_t)((R.spans[2 * j] >> R.bl) + (g - R.cnt_ptr[j])));
   }
   __syncthreads();
-  // dependency closure, one round per pass over the entries listed so far
+  // dependency closure, one round per pass over the entries listed so far.
+  // Every thread reads the round's tail between two barriers, before anyone
+  // pushes in this round: a wave reading it after another wave's pushes would
+  // see a longer list, and threads leaving the loop in different rounds would
+  // meet at different barriers.
   uint32_t head = 0;
   for (uint32_t round = 0; round <= R.n_blocks; round++) {
     const uint32_t tail = min(s_tail, (uint32_t)R.n_blocks);
+    __syncthreads();
     if (head >= tail) break;
     for (uint32_t i = head + t; i < tail; i += kPlanWG) {
       const uint32_t b = (uint32_t)R.list[i];
