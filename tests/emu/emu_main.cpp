@@ -83,6 +83,73 @@ int main(int argc, char** argv) {
     std::free(offsets);
     std::free(r);
   }
+  // the eight-kernel request path (planning in one workgroup switched off)
+  lz_tuning tu;
+  CHECK(lz_get_tuning(h, &tu));
+  tu.plan_blocks = 1;
+  CHECK(lz_set_tuning(h, &tu));
+  for (int k = 0; k < 3; k++) {
+    uint8_t* r = aligned(lens[k] + 256);
+    std::memset(scr, 0xAA, scr_len);
+    CHECK(lz_decode_range(h, offs[k], lens[k], r, scr, scr_len, nullptr));
+    CHECK(lz_sync_status(h, nullptr));
+    if (std::memcmp(r, src.data() + offs[k], lens[k])) { std::fprintf(stderr, "range %d differs (8 kernels)\n", k); return 1; }
+    std::free(r);
+  }
+  // a batch of two ranges (and two reads when there is a read index)
+  {
+    const int nreq = info.n_reads ? 4 : 2;
+    lz_request* rq = (lz_request*)aligned(sizeof(lz_request) * 4);
+    rq[0] = lz_request{1, (int64_t)(N / 5), (int64_t)(N / 5 < 1000 ? N / 5 : 1000)};
+    rq[1] = lz_request{1, 0, (int64_t)(N < 700 ? N : 700)};
+    if (info.n_reads) {
+      rq[2] = lz_request{0, 0, 0};
+      rq[3] = lz_request{0, (int64_t)info.n_reads - 1, 0};
+    }
+    uint32_t* dn = (uint32_t*)aligned(4);
+    *dn = (uint32_t)nreq;
+    uint64_t* offsets = (uint64_t*)aligned(8 * 5);
+    const uint64_t cap = 2000 + 2 * (uint64_t)info.max_record_len;
+    uint8_t* r = aligned(cap);
+    for (uint32_t pb : {4096u, 1u}) {
+      tu.plan_blocks = pb;
+      CHECK(lz_set_tuning(h, &tu));
+      std::memset(scr, 0xAA, scr_len);
+      CHECK(lz_decode_batch(h, rq, dn, nreq, r, cap, offsets, scr, scr_len, nullptr));
+      CHECK(lz_sync_status(h, nullptr));
+      std::vector<uint8_t> want;
+      for (int k = 0; k < nreq; k++) {
+        uint64_t a0 = (uint64_t)rq[k].a, b0 = a0 + (uint64_t)rq[k].b;
+        if (rq[k].kind == 0) {
+          std::vector<uint64_t> rs{0};
+          int lines = 0;
+          for (uint64_t i = 0; i < N; i++)
+            if (src[i] == '\n' && ++lines % 4 == 0) rs.push_back(i + 1);
+          a0 = rs[rq[k].a];
+          b0 = rs[rq[k].a + 1];
+        }
+        want.insert(want.end(), src.begin() + a0, src.begin() + b0);
+      }
+      if (offsets[nreq] != want.size() || std::memcmp(r, want.data(), want.size())) {
+        std::fprintf(stderr, "batch differs (plan_blocks %u)\n", pb);
+        return 1;
+      }
+    }
+    std::free(rq);
+    std::free(dn);
+    std::free(offsets);
+    std::free(r);
+  }
+  // device verification hash
+  {
+    uint64_t* tree = (uint64_t*)aligned(8);
+    uint8_t* vs = aligned(8 * info.n_blocks + 8);
+    CHECK(lz_verify(h, out, tree, vs, 8 * info.n_blocks + 8, nullptr));
+    CHECK(lz_sync_status(h, nullptr));
+    if (*tree != info.source_fnv) { std::fprintf(stderr, "verification tree differs\n"); return 1; }
+    std::free(tree);
+    std::free(vs);
+  }
   lz_close(h);
   std::free(arc);
   std::free(ws);
