@@ -265,7 +265,7 @@ __device__ bool short_rans(const uint8_t* body, const Stream& s, uint32_t P, con
 // clamped into the group (a group without words reads the first state
 // instead), so every load stays inside the record; a corrupt stream that
 // consumes more words than the group holds fails pos == nwg.
-constexpr uint32_t kPreSlices = 6;
+constexpr uint32_t kPreSlices = 3;
 struct LitPre {
   uint32_t w[2 * kPreSlices];   // w[2 s + h] = word 128 s + 64 h + lane
   uint32_t x, woff, nwg;
@@ -328,9 +328,11 @@ __device__ bool lit_group(const uint8_t* body, uint32_t K, uint32_t n, uint32_t 
       ringe[64 * q + lane] = en[q];
     }
   }
-  uint32_t rq[2 * kPreSlices - 4];
-#pragma unroll
-  for (uint32_t q = 0; q < 2 * kPreSlices - 4; q++) rq[q] = L.w[4 + q];
+  // slice 2 waits in registers (u0, u1); staging it loads the next slice
+  // straight into the same registers, so no register moves follow the loads
+  // and their wait falls one slice later
+  static_assert(kPreSlices == 3, "the ring holds slices 0 and 1, registers slice 2");
+  uint32_t u0 = L.w[4], u1 = L.w[5];
   uint32_t e = S.lut[x & mask];
   uint32_t pos = 0;
   const uint32_t R = n / K, ex = n - R * K;
@@ -369,24 +371,7 @@ __device__ bool lit_group(const uint8_t* body, uint32_t K, uint32_t n, uint32_t 
     const uint32_t w = ring[q];
     e = need ? ringe[q] : S.lut[x & mask];
     x = need ? (x << 16) | w : x;
-    if (bal) {
-      const uint32_t s0 = pos >> 7;
-      pos += (uint32_t)__popcll(bal);
-      if ((pos >> 7) != s0) {            // entered slice s0+1: stage s0+2, fetch s0+kPreSlices
-        __builtin_amdgcn_wave_barrier(); // after every lane's read of slice s0
-        const uint32_t ea = S.lut[rq[0] & mask], eb = S.lut[rq[1] & mask];
-        const uint32_t d = ((s0 & 1) << 7) + lane;
-        ring[d] = (uint16_t)rq[0];
-        ring[d + 64] = (uint16_t)rq[1];
-        ringe[d] = ea;
-        ringe[d + 64] = eb;
-#pragma unroll
-        for (uint32_t q = 0; q + 2 < 2 * kPreSlices - 4; q++) rq[q] = rq[q + 2];
-        const uint32_t b3 = (s0 + kPreSlices) << 7;
-        rq[2 * kPreSlices - 6] = ldw(b3 + lane);
-        rq[2 * kPreSlices - 5] = ldw(b3 + 64 + lane);
-      }
-    }
+    pos += (uint32_t)__popcll(bal);
     // end of the lane's literal run in this sequence: the next sequence
     // with literals (every literal index below n_lit has one), from the
     // register queue while it lasts, else from the tables
@@ -407,12 +392,36 @@ __device__ bool lit_group(const uint8_t* body, uint32_t K, uint32_t n, uint32_t 
       }
     }
   };
-  if (FULL) {
-    for (uint32_t r = 0; r < R; r++) round(true);
-  } else {
-    for (uint32_t r = 0; r < R; r++) round(lane_ok);
+  // A round that enters slice s0+1 stages slice s0+2 from the registers into
+  // the ring half of slice s0 and loads slice s0+kPreSlices into them. Written
+  // out in this scope: inside the round helper, which takes its state by
+  // reference, the registers would be spilled to a private array.
+#define LZ_ROUND(act)                                                   \
+  {                                                                     \
+    const uint32_t s0 = pos >> 7;                                       \
+    round(act);                                                         \
+    if ((pos >> 7) != s0) {                                             \
+      __builtin_amdgcn_wave_barrier(); /* every lane read slice s0 */   \
+      const uint32_t d = ((s0 & 1) << 7) + lane;                        \
+      const uint32_t b3 = (s0 + kPreSlices) << 7;                       \
+      const uint32_t ea = S.lut[u0 & mask], eb = S.lut[u1 & mask];      \
+      ring[d] = (uint16_t)u0;                                           \
+      ring[d + 64] = (uint16_t)u1;                                      \
+      ringe[d] = ea;                                                    \
+      ringe[d + 64] = eb;                                               \
+      if (b3 < nwg) {                  /* words left to fetch */        \
+        u0 = ldw(b3 + lane);                                            \
+        u1 = ldw(b3 + 64 + lane);                                       \
+      }                                                                 \
+    }                                                                   \
   }
-  if (ex) round(lane_ok && k < ex);
+  if (FULL) {
+    for (uint32_t r = 0; r < R; r++) LZ_ROUND(true)
+  } else {
+    for (uint32_t r = 0; r < R; r++) LZ_ROUND(lane_ok)
+  }
+  if (ex) round(lane_ok && k < ex);     // no read follows: nothing to stage
+#undef LZ_ROUND
   ok = ok && (!lane_ok || x == kL) && pos == nwg;
   return __ballot(!ok) == 0;
 }
@@ -598,7 +607,7 @@ __device__ __forceinline__ void put_prep(Smem& S, const BlockDir& d, const Strea
 // into the tile (free until the literal stage) with one round of 16-byte
 // loads; waves 0..2 decode the short streams from there (at most about 9.3 KB
 // with their headers for 1025 sequences).  Corrupt records are latched.
-__device__ void prep_tile(Smem& S, const DevArgs& A, uint32_t b) {
+__device__ __forceinline__ void prep_tile(Smem& S, const DevArgs& A, uint32_t b) {
   const uint32_t t = threadIdx.x, wv = uni(t >> 6), lane = lane_id();
   const BlockDir d = block_dir(A, b);
   const uint8_t* pay = A.arc + A.off_payload + d.poff;
@@ -639,7 +648,7 @@ __device__ void prep_tile(Smem& S, const DevArgs& A, uint32_t b) {
 // counts (or corrupt records) leaves S.pok 0, and the block is prepared again
 // by prep_tile.  The caller guarantees that the sequence tables, S.pst and
 // the rings are not in use.
-__device__ void prep_ring(Smem& S, const DevArgs& A, uint32_t b) {
+__device__ __forceinline__ void prep_ring(Smem& S, const DevArgs& A, uint32_t b) {
   const uint32_t wv = uni(threadIdx.x >> 6), lane = lane_id();
   const BlockDir d = block_dir(A, b);
   const uint8_t* pay = A.arc + A.off_payload + d.poff;
@@ -673,7 +682,7 @@ __device__ void prep_ring(Smem& S, const DevArgs& A, uint32_t b) {
 // been prepared meanwhile, by waves 1..3 while wave 0 resolved b's in-block
 // matches.  Every loop below is bounded by values read from global memory
 // (directory, stream headers).
-__device__ bool decode_block(Smem& S, const DevArgs& A, uint32_t b, uint32_t nb) {
+__device__ __forceinline__ bool decode_block(Smem& S, const DevArgs& A, uint32_t b, uint32_t nb) {
   const uint32_t t = threadIdx.x, wv = uni(t >> 6), lane = lane_id();
   const uint64_t B = 1ull << A.bl, sb = (uint64_t)b << A.bl;
   const uint32_t blen = (uint32_t)((sb + B <= A.n) ? B : A.n - sb);
@@ -1109,7 +1118,7 @@ __device__ bool decode_block(Smem& S, const DevArgs& A, uint32_t b, uint32_t nb)
 
 
 // Once per workgroup: literal LUT image into LDS, small-stream cumulative tables.
-__device__ void load_tables(Smem& S, const DevArgs& A) {
+__device__ __forceinline__ void load_tables(Smem& S, const DevArgs& A) {
   const uint4* s = reinterpret_cast<const uint4*>(A.lut);
   uint4* d = reinterpret_cast<uint4*>(S.lut);
   for (uint32_t c = threadIdx.x; c < kLutLit / 4; c += kWG) d[c] = s[c];
@@ -1149,7 +1158,7 @@ __device__ void load_tables(Smem& S, const DevArgs& A) {
 // arrival and acquire after the wait make the blocks decoded before the
 // barrier visible to every workgroup after it.  A wait longer than the spin
 // limit latches the watchdog and lets the kernel finish (status ECORRUPT).
-__device__ void grid_barrier(uint32_t* ctl, uint32_t target, uint32_t spin_limit) {
+__device__ __forceinline__ void grid_barrier(uint32_t* ctl, uint32_t target, uint32_t spin_limit) {
   __syncthreads();
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");

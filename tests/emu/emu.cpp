@@ -111,7 +111,9 @@ void finish(Group::Wave& w, int wbase) {
         const int row = l >> 4, i = l & 15, bank = (l >> 2) & 3;
         const uint32_t old = (uint32_t)(w.val[l] >> 32);
         int src = -1;
-        if (ctrl >= 0x111 && ctrl <= 0x11F) {                // row_shr:n
+        if (ctrl >= 0 && ctrl <= 0xFF) {                     // quad_perm
+          src = (l & ~3) | ((ctrl >> (2 * (l & 3))) & 3);
+        } else if (ctrl >= 0x111 && ctrl <= 0x11F) {         // row_shr:n
           const int n = ctrl & 0xF;
           if (i >= n) src = l - n;
         } else if (ctrl == 0x142) {                          // row_bcast:15

@@ -87,7 +87,14 @@ __attribute__((noinline)) inline unsigned long long __shfl_up(unsigned long long
 __attribute__((noinline)) inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int rm, int bm, bool bc) {
   return emu_update_dpp(old, src, ctrl, rm, bm, bc, EMU_SITE);
 }
+__attribute__((noinline)) inline int __builtin_amdgcn_mov_dpp(int src, int ctrl, int rm, int bm, bool bc) {
+  // identity quad_perm with every row and bank written: each lane reads its
+  // own register, so it is lane-local and legal in divergent code
+  if (ctrl == 0xE4 && rm == 0xF && bm == 0xF) return src;
+  return emu_update_dpp(0, src, ctrl, rm, bm, bc, EMU_SITE);
+}
 __attribute__((noinline)) inline void __builtin_amdgcn_wave_barrier() { emu_wave_barrier(EMU_SITE); }
+inline void __builtin_amdgcn_sched_barrier(int) { }
 __attribute__((noinline)) inline void __builtin_amdgcn_fence(int order, const char* scope) {
   if (scope && !std::strcmp(scope, "wavefront")) emu_wave_barrier(EMU_SITE);
   else std::atomic_thread_fence(std::memory_order_seq_cst);
