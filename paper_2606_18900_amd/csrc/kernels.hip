@@ -875,34 +875,12 @@ __device__ __forceinline__ bool decode_block(Smem& S, const DevArgs& A, uint32_t
           const uint8_t* p = A.out + of + k0 + sub;
 #pragma unroll
           for (uint32_t u = 0; u < 32; u++) v[u] = k0 + sub + 8 * u < M ? (uint32_t)p[8 * u] : 0u;
-        } else if (k0 + sub < M) {           // request mode: bases from the address table
-          // the lane's bytes of this chunk, k = kf + 8 u < M, lie in blocks
-          // bf..bl; when that is at most two blocks their two bases are read
-          // once, so the 32 byte loads go out together (per-byte lookups
-          // would wait for the table before every byte)
-          const uint32_t kf = k0 + sub, kl = kf + 8 * min(31u, (M - 1 - kf) >> 3);
-          const uint64_t bf = (of + kf) >> A.bl, bl = (of + kl) >> A.bl;
-          if (bl - bf <= 1) {
-            const uint64_t base0 = A.addr[bf], base1 = A.addr[bl];
-            const uint64_t lo = (1ull << A.bl) - 1;
-#pragma unroll
-            for (uint32_t u = 0; u < 32; u++) {
-              const uint32_t k = kf + 8 * u;
-              const uint64_t a = of + k;
-              const uint64_t base = (a >> A.bl) == bf ? base0 : base1;
-              if (k < M && !base) bad = true;
-              v[u] = k < M && base ? (uint32_t)reinterpret_cast<const uint8_t*>(base)[a & lo] : 0u;
-            }
-          } else {                           // blocks shorter than the chunk
-#pragma unroll
-            for (uint32_t u = 0; u < 32; u++) {
-              const uint32_t k = kf + 8 * u;
-              v[u] = k < M ? src_byte(A, of + k, bad) : 0u;
-            }
-          }
         } else {
 #pragma unroll
-          for (uint32_t u = 0; u < 32; u++) v[u] = 0u;
+          for (uint32_t u = 0; u < 32; u++) {
+            const uint32_t k = k0 + sub + 8 * u;
+            v[u] = k < M ? src_byte(A, of + k, bad) : 0u;
+          }
         }
 #pragma unroll
         for (uint32_t u = 0; u < 32; u++) {
