@@ -376,6 +376,66 @@ def big_genome_leg(args, dev):
             pass
 
 
+def deep_leg(x: bytes, starts, args, dev, threads: int, steps: int = 10) -> dict:
+    """Whole-file decode at full dependency depth: the first 256 MiB of the
+    FASTQ (whole records) encoded without the level penalty (beta = 0), so
+    short header matches reach into earlier blocks and the levels climb to
+    the cap of 64.  Both launch modes, bit-exact (host compare and device FNV
+    tree), mean of `steps` decodes timed with HIP events."""
+    import numpy as np
+    import torch
+
+    import paper_2606_18900_amd as lz
+    k = int(np.searchsorted(np.asarray(starts), 256 << 20))
+    xs = x[:int(starts[min(k, len(starts) - 1)])]
+    cached = os.path.join(args.cache, "fastq_deep_%d_seed2.lz" % len(xs)) if args.cache else None
+    t0 = time.time()
+    if cached and os.path.exists(cached):
+        with open(cached, "rb") as f:
+            a = f.read()
+    else:
+        a = lz.encode(xs, threads=threads, **dict(FASTQ_PARAMS, level_penalty=0))
+        if cached:
+            os.makedirs(args.cache, exist_ok=True)
+            with open(cached, "wb") as f:
+                f.write(a)
+    enc_s = time.time() - t0
+    arc = lz.Archive(a, device=dev)
+    N = arc.n
+    out = torch.empty(N + 256, dtype=torch.uint8, device=dev)
+    src = np.frombuffer(xs, dtype=np.uint8)
+    stream = torch.cuda.current_stream()
+    res = {"bytes": N, "levels": int(arc.info.n_levels), "blocks": int(arc.info.n_blocks),
+           "ratio": round(N / len(a), 4), "encode_s": round(enc_s, 1),
+           "what": "first 256 MiB of the FASTQ, level penalty 0 (levels up to the cap of 64)"}
+    for mode, name in ((0, "per_level_gbps"), (1, "persistent_gbps")):
+        arc.set_tuning(sync_mode=mode, wg_per_cu=3)
+        out.zero_()
+        arc.decode_all(out)
+        torch.cuda.synchronize()
+        arc.sync_status()
+        if not np.array_equal(out[:N].cpu().numpy(), src):
+            raise RuntimeError("deep archive: decode mismatch (mode %d)" % mode)
+        tree = int(arc.verify(out).cpu().item()) & 0xFFFFFFFFFFFFFFFF
+        arc.sync_status()
+        if tree != int(lz.info(a).source_fnv):
+            raise RuntimeError("deep archive: FNV tree mismatch (mode %d)" % mode)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+        arc.decode_all(out)
+        for e0, e1 in evs:
+            e0.record(stream)
+            arc.decode_all(out)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        arc.sync_status()
+        ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+        res[name] = round(N / (ms / 1e3) / 1e9, 1)
+    log("deep FASTQ (beta 0): %d levels, ratio %.3f; per-level launches %.1f GB/s, persistent %.1f GB/s"
+        % (res["levels"], res["ratio"], res["per_level_gbps"], res["persistent_gbps"]))
+    return res
+
+
 def split_leg(x: bytes, a_mono: bytes, args, dev, threads: int, steps: int = 10) -> dict:
     """Stream-separated FASTQ container of the same file (ids, sequences, '+'
     lines and qualities as four archives, Discussion: "Where ACEAPEX Stands
@@ -567,7 +627,7 @@ def main() -> int:
     ap.add_argument("--bytes", type=int, default=1 << 30, help="FASTQ size (default 1 GiB)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", choices=("all", "decode", "copy", "serve", "genome", "biggenome", "reads",
-                                       "split"),
+                                       "split", "deep"),
                     default="all",
                     help="decode: only the whole-file decode in the reported launch mode "
                          "(for profiling; no range leg, no CPU baseline); copy: a plain "
@@ -663,6 +723,9 @@ def main() -> int:
         return stage_clocks(arc, out)
     if args.legs == "split":
         print(json.dumps({"split_fastq": split_leg(x, a, args, dev, threads)}), flush=True)
+        return 0
+    if args.legs == "deep":
+        print(json.dumps({"deep_fastq": deep_leg(x, starts, args, dev, threads)}), flush=True)
         return 0
 
     def run(mode: int, wg: int, steps: int, warmup: int):
@@ -762,9 +825,10 @@ def main() -> int:
     if args.legs == "all":
         served = serving(arc, starts, dev)
 
-    split = None
+    split = deep = None
     if args.legs == "all":
         split = split_leg(x, a, args, dev, threads)
+        deep = deep_leg(x, starts, args, dev, threads)
 
     # algorithmic bytes of one decode: compressed payload + directory +
     # dependency lists read, match-source bytes, output bytes
@@ -839,6 +903,7 @@ def main() -> int:
         "batched_lookups": batch_res,
         "serving": served,
         "split_fastq": split,
+        "deep_fastq": deep,
         "encode_s": round(enc_s, 1),
     }
     print(json.dumps(line), flush=True)
