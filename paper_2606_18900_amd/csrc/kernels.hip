@@ -133,6 +133,17 @@ __device__ __forceinline__ uint64_t ld64(const uint8_t* p) {
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63; }
+// 16 bytes per lane straight from global memory into LDS, without registers
+// (global_load_lds_dwordx4): lane k's bytes land at dst + 16 k, dst being the
+// wave's uniform LDS address.  The compiler does not track the LDS write:
+// lds_dma_wait() (vmcnt(0)) must come before any read of the bytes.
+__device__ __forceinline__ void lds_dma16(const void* src, void* dst) {
+  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                   (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+}
+__device__ __forceinline__ void lds_dma_wait() {
+  __builtin_amdgcn_s_waitcnt(0xF70);   // vmcnt(0), expcnt and lgkmcnt untouched
+}
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 __device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
@@ -614,10 +625,20 @@ __device__ __forceinline__ void prep_tile(Smem& S, const DevArgs& A, uint32_t b)
   CLK_START(S);
   const uint32_t hlen = min(d.plen, kB);
   {
-    const uint4* src4 = reinterpret_cast<const uint4*>(pay);
-    uint4* dst4 = reinterpret_cast<uint4*>(S.tile);
-    for (uint32_t c = t; c < (hlen >> 4); c += kWG) dst4[c] = src4[c];
-    if (t < (hlen & 15u)) S.tile[(hlen & ~15u) + t] = pay[(hlen & ~15u) + t];
+    const uint32_t n16 = hlen >> 4;
+    const bool tail = t < (hlen & 15u);              // bytes past the last 16
+    const uint32_t tb = tail ? (uint32_t)pay[(hlen & ~15u) + t] : 0u;
+    if (((uintptr_t)pay & 15u) == 0) {   // straight into LDS, one HBM round trip
+#pragma unroll 1
+      for (uint32_t i = 0; i < kB / (16 * kWG); i++)
+        if (t + kWG * i < n16) lds_dma16(pay + 16 * (t + kWG * i), S.tile + 16 * (64 * wv + kWG * i));
+      lds_dma_wait();
+    } else {
+      const uint4* src4 = reinterpret_cast<const uint4*>(pay);
+      uint4* dst4 = reinterpret_cast<uint4*>(S.tile);
+      for (uint32_t c = t; c < n16; c += kWG) dst4[c] = src4[c];
+    }
+    if (tail) S.tile[(hlen & ~15u) + t] = (uint8_t)tb;
   }
   if (t == 0) S.next = 0;
   __syncthreads();
@@ -654,10 +675,23 @@ __device__ __forceinline__ void prep_ring(Smem& S, const DevArgs& A, uint32_t b)
   const uint8_t* pay = A.arc + A.off_payload + d.poff;
   const uint32_t hlen = min(d.plen, kPrepRing);
   {
-    const uint4* src4 = reinterpret_cast<const uint4*>(pay);
-    uint4* dst4 = reinterpret_cast<uint4*>(S.prep);
-    for (uint32_t c = lane; c < (hlen >> 4); c += 64) dst4[c] = src4[c];
-    if (lane < (hlen & 15u)) S.prep[(hlen & ~15u) + lane] = pay[(hlen & ~15u) + lane];
+    const uint32_t n16 = hlen >> 4;
+    const bool tail = lane < (hlen & 15u);           // bytes past the last 16
+    const uint32_t tb = tail ? (uint32_t)pay[(hlen & ~15u) + lane] : 0u;
+    if (((uintptr_t)pay & 15u) == 0) {
+      // every 1 KiB of the prefix at once, straight into LDS: one HBM round
+      // trip (copied through registers it was one per 1 KiB, as the
+      // registers are all taken here)
+#pragma unroll 1
+      for (uint32_t i = 0; i < kPrepRing / 1024; i++)   // not unrolled: no hoisted addresses
+        if (lane + 64 * i < n16) lds_dma16(pay + 16 * (lane + 64 * i), S.prep + 1024 * i);
+      lds_dma_wait();
+    } else {
+      const uint4* src4 = reinterpret_cast<const uint4*>(pay);
+      uint4* dst4 = reinterpret_cast<uint4*>(S.prep);
+      for (uint32_t c = lane; c < n16; c += 64) dst4[c] = src4[c];
+    }
+    if (tail) S.prep[(hlen & ~15u) + lane] = (uint8_t)tb;
   }
   __builtin_amdgcn_wave_barrier();
   Stream sc, sm, so, sl;
@@ -1119,10 +1153,12 @@ __device__ __forceinline__ bool decode_block(Smem& S, const DevArgs& A, uint32_t
 
 // Once per workgroup: literal LUT image into LDS, small-stream cumulative tables.
 __device__ __forceinline__ void load_tables(Smem& S, const DevArgs& A) {
-  const uint4* s = reinterpret_cast<const uint4*>(A.lut);
-  uint4* d = reinterpret_cast<uint4*>(S.lut);
-  for (uint32_t c = threadIdx.x; c < kLutLit / 4; c += kWG) d[c] = s[c];
-  const uint32_t t = threadIdx.x;
+  const uint32_t t = threadIdx.x, wv = uni(t >> 6);
+  // the LUT image (256-byte aligned in the workspace) straight into LDS
+  static_assert(kLutLit % (4 * kWG) == 0, "whole LUT rounds");
+#pragma unroll 1
+  for (uint32_t i = 0; i < kLutLit / (4 * kWG); i++)
+    lds_dma16(A.lut + 4 * (t + kWG * i), S.lut + 4 * (64 * wv + kWG * i));
   if (t < 3 * 64) {          // waves 0..2: one table each, 4 symbols per lane
     const uint32_t k = t >> 6, lane = t & 63;
     const uint8_t* tab = A.arc + A.off_tables + 512 * (k + 1);
@@ -1143,6 +1179,7 @@ __device__ __forceinline__ void load_tables(Smem& S, const DevArgs& A) {
     }
     if (lane == 63) S.cum[k][256] = (uint16_t)min(c, 65535u);
   }
+  lds_dma_wait();                      // this wave's LUT rows, before the barrier
   __syncthreads();
   // bucket index of each short stream: bucket b starts at slot b << bs
   for (uint32_t e = t; e < 3 * 256; e += kWG) {

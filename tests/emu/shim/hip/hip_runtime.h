@@ -95,6 +95,13 @@ __attribute__((noinline)) inline int __builtin_amdgcn_mov_dpp(int src, int ctrl,
 }
 __attribute__((noinline)) inline void __builtin_amdgcn_wave_barrier() { emu_wave_barrier(EMU_SITE); }
 inline void __builtin_amdgcn_sched_barrier(int) { }
+// global_load_lds: lane k's `size` bytes from src land at dst + off + size k
+// (dst is the wave's uniform LDS address); the copy is done at once, so the
+// wait that the device needs before reading is a no-op here
+inline void __builtin_amdgcn_global_load_lds(const void* src, void* dst, unsigned size, int off, int) {
+  std::memcpy(static_cast<char*>(dst) + off + size * (threadIdx.x & 63u), src, size);
+}
+inline void __builtin_amdgcn_s_waitcnt(int) { }
 __attribute__((noinline)) inline void __builtin_amdgcn_fence(int order, const char* scope) {
   if (scope && !std::strcmp(scope, "wavefront")) emu_wave_barrier(EMU_SITE);
   else std::atomic_thread_fence(std::memory_order_seq_cst);
