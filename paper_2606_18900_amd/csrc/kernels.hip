@@ -1025,6 +1025,8 @@ __device__ __forceinline__ bool decode_block(Smem& S, const DevArgs& A, uint32_t
   const bool ov = small && nb != ~0u;
   const uint64_t c4_ = CLK_NOW();
   if (wv == 0 && cnt) {
+    // wave 0's passes bound this stage: it wins issue on its SIMD meanwhile
+    __builtin_amdgcn_s_setprio(2);
     if (small) {                             // fields from stage 2 (before two barriers)
       if (a0 < a1) {
         const uint32_t pk = Fp[a0];
@@ -1120,6 +1122,7 @@ __device__ __forceinline__ bool decode_block(Smem& S, const DevArgs& A, uint32_t
       if (__ballot(pending)) bad = true;      // unreachable for a valid block
     }
     if (bad) S.err = 1;
+    __builtin_amdgcn_s_setprio(0);
     CLK_ADD(S, 13, CLK_NOW() - c4_);
   } else if (wv != 0 && ov) {
     prep_ring(S, A, nb);

@@ -102,6 +102,7 @@ inline void __builtin_amdgcn_global_load_lds(const void* src, void* dst, unsigne
   std::memcpy(static_cast<char*>(dst) + off + size * (threadIdx.x & 63u), src, size);
 }
 inline void __builtin_amdgcn_s_waitcnt(int) { }
+inline void __builtin_amdgcn_s_setprio(int) { }
 __attribute__((noinline)) inline void __builtin_amdgcn_fence(int order, const char* scope) {
   if (scope && !std::strcmp(scope, "wavefront")) emu_wave_barrier(EMU_SITE);
   else std::atomic_thread_fence(std::memory_order_seq_cst);
