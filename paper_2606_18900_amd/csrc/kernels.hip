@@ -1122,10 +1122,14 @@ __device__ __forceinline__ bool decode_block(Smem& S, const DevArgs& A, uint32_t
       if (__ballot(pending)) bad = true;      // unreachable for a valid block
     }
     if (bad) S.err = 1;
-    __builtin_amdgcn_s_setprio(0);
+    __builtin_amdgcn_s_setprio(1);
     CLK_ADD(S, 13, CLK_NOW() - c4_);
   } else if (wv != 0 && ov) {
+    // the preparation has slack (it ends well before wave 0's passes): it
+    // yields issue to the waves on their workgroups' critical paths
+    __builtin_amdgcn_s_setprio(0);
     prep_ring(S, A, nb);
+    __builtin_amdgcn_s_setprio(1);
     CLK_ADD1(S, 14, CLK_NOW() - c4_);
   }
   __syncthreads();
@@ -1225,6 +1229,9 @@ __device__ __forceinline__ void grid_barrier(uint32_t* ctl, uint32_t target, uin
 // kernel's register budget is that of one copy of it.
 __global__ void __launch_bounds__(kWG, 3) k_decode(DevArgs A) {   // 3 waves per SIMD: at most 168 VGPRs
   __shared__ Smem S;
+  // issue priority: 1 by default, 2 for wave 0's in-block passes, 0 for the
+  // next block's preparation by waves 1..3 (the one stage with slack)
+  __builtin_amdgcn_s_setprio(1);
   const uint32_t t = threadIdx.x;
   uint32_t it = 0, qe = 0, L = 0, bars = 0;
   bool pending = false;       // (persistent) a non-empty level has been started
