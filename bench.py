@@ -31,8 +31,8 @@ HBM_PEAK_GBPS = 8000.0      # MI355X HBM3E
 # decode), each scaled by what the same counter reads for a 1 GiB device copy
 # (`bench.py --legs copy`: FETCH_SIZE x 1.99995, WRITE_SIZE x 1.0).  Reported
 # only while the decoder source is the one the counters were taken on.
-PMC_TRAFFIC = {"kernels_sha256_16": "26814b6445ae1e14", "bytes": 1 << 30,
-               "fetch": 604533497, "write": 1073741536}
+PMC_TRAFFIC = {"kernels_sha256_16": "bd7fcdca2841bb4d", "bytes": 1 << 30,
+               "fetch": 603599826, "write": 1073741536}
 
 
 def log(msg: str) -> None:
